@@ -1,0 +1,141 @@
+/* stiffchem -- batched stiff chemistry integration on MI355X (gfx950).
+ *
+ * Every CFD cell is integrated as an independent homogeneous gas-phase
+ * reactor (paper Sec. 1: one reactor per cell, cost proportional to the cell
+ * count; Sec. 2.1, Eqs. 3-4: the species and heat source terms come from that
+ * integration).  The reactor here is adiabatic, ideal-gas and at constant
+ * pressure; its state is (T, Y_1..Y_N).  The integrator is a linearly implicit
+ * (Rosenbrock) method fed by an analytical Jacobian (Sec. 2.5: sparse
+ * analytical Jacobian, per-cell local time steps).
+ *
+ * Conventions for every call:
+ *   - units are SI: T [K], p [Pa], Y [-], dt [s];
+ *   - array arguments of sc_rhs, sc_jacobian, sc_linsolve, sc_integrate and
+ *     sc_adjoint are DEVICE pointers on the plan's device, owned by the
+ *     caller; mass fractions are species-major, Y[k * ld + c] for species k
+ *     of cell c (ld >= n);
+ *   - argument errors are returned synchronously, before any launch, with a
+ *     message from sc_last_error(); device work is asynchronous on the given
+ *     HIP stream (NULL = the default stream) and the caller synchronises;
+ *   - per-cell failures never fail a call: they set the cell's status code;
+ *   - no C++ exception or abort crosses this interface.
+ * The library owns only sc_mech, sc_plan and its internal workspace.
+ */
+#ifndef STIFFCHEM_H
+#define STIFFCHEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SC_OK = 0,
+    SC_EINVAL = -1,       /* bad argument (NULL pointer, negative size, ...) */
+    SC_EPARSE = -2,       /* malformed or inconsistent mechanism text */
+    SC_ENOMEM = -3,       /* device or host allocation failed */
+    SC_EHIP = -4,         /* a HIP runtime call failed */
+    SC_EUNSUPPORTED = -5, /* mechanism larger than the kernels support */
+    SC_EBUDGET = -6       /* adjoint checkpoints exceed the memory budget */
+} sc_status;
+
+/* per-cell status codes written by sc_integrate / sc_adjoint */
+enum {
+    SC_CELL_OK = 0,
+    SC_CELL_MAX_STEPS = 1,   /* max_steps reached before t = dt */
+    SC_CELL_H_UNDERFLOW = 2, /* step size fell below 1e-20 dt */
+    SC_CELL_NONFINITE = 3,   /* five consecutive non-finite error estimates */
+    SC_CELL_BAD_INPUT = 4    /* non-finite or non-positive T, p; dt < 0; non-finite Y */
+};
+
+/* integration modes */
+enum {
+    SC_MODE_PLAIN = 0,     /* one workgroup per cell, grid = cells */
+    SC_MODE_PERSISTENT = 1 /* resident grid pulling cell tiles from a queue */
+};
+
+typedef struct sc_mech sc_mech; /* immutable after load; shareable across threads */
+typedef struct sc_plan sc_plan; /* a mechanism on one device; one stream at a time */
+
+typedef struct {
+    double rtol;        /* relative tolerance (default 1e-6) */
+    double atol;        /* absolute tolerance, every component (default 1e-12) */
+    int32_t max_steps;  /* accepted + rejected steps per cell (default 100000) */
+    int32_t mode;       /* SC_MODE_PLAIN or SC_MODE_PERSISTENT */
+    int32_t tile;       /* persistent mode: cells per queue pull (default 1) */
+    int32_t grid;       /* persistent mode: workgroups; 0 = resident capacity */
+    int32_t order;      /* persistent mode: 1 = pull cells longest-dt first */
+    int32_t reserved;
+} sc_options;
+
+typedef struct {
+    int32_t n_species, n_reactions, n_third_body, n_troe, n_elements;
+    int32_t n_state;    /* N + 1 */
+    int32_t n_padded;   /* register rows per cell used by the kernels */
+    int32_t nnz_jac;    /* structural nonzeros of the (N+1)^2 Jacobian */
+    int32_t nnz_lu;     /* nonzeros of L+U in the kernels' factorisation order */
+    int32_t n_stages;   /* Rosenbrock stages per step */
+    int32_t rhs_evals_per_step;
+    int32_t exp_per_rhs;  /* exp/log/pow calls per right-hand side */
+    int64_t flops_rhs;    /* per right-hand side, transcendental calls excluded */
+    int64_t flops_jac;    /* analytical Jacobian assembly */
+    int64_t flops_lu;     /* one factorisation as the kernel schedules it */
+    int64_t flops_solve;  /* one forward + back substitution */
+    int64_t flops_step;   /* one Rosenbrock step (Jacobian, LU, stages, control) */
+} sc_mech_info;
+
+void sc_default_options(sc_options *opt);
+
+/* Parse, validate and compile a mechanism (text format: see the package
+ * docs; units of the rate law as in the paper's CHEMKIN-style mechanisms:
+ * log10 A in cgs, Ea in J/mol).  Host only.  On error *out is NULL and
+ * SC_EPARSE / SC_EUNSUPPORTED is returned with a message. */
+sc_status sc_mech_load(const char *text, size_t len, sc_mech **out);
+sc_status sc_mech_info_get(const sc_mech *mech, sc_mech_info *out);
+/* index of a species by name, or SC_EINVAL */
+sc_status sc_species_index(const sc_mech *mech, const char *name, int32_t *idx);
+void sc_mech_free(sc_mech *mech);
+
+/* Upload a mechanism's tables to a device (hipSetDevice(device) is made
+ * current for the call) and pick the kernel variant. */
+sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt, sc_plan **out);
+void sc_plan_free(sc_plan *plan);
+
+/* Right-hand side at n states (thermo, rates, production rates; the reactor
+ * ODE of every cell): fT[c] = dT/dt, fY[k*ld + c] = dY_k/dt.  dlnA: R
+ * per-reaction log multipliers of the net rate, or NULL. */
+sc_status sc_rhs(sc_plan *plan, int64_t n, const double *T, const double *p, const double *Y,
+                 int64_t ld, const double *dlnA, double *fT, double *fY, void *hip_stream);
+
+/* Analytical Jacobian of the same right-hand side with respect to the state
+ * (Y_0..Y_{N-1}, T): J[c*(N+1)*(N+1) + i*(N+1) + j] = d f_i / d y_j, with
+ * index N standing for T. */
+sc_status sc_jacobian(sc_plan *plan, int64_t n, const double *T, const double *p, const double *Y,
+                      int64_t ld, const double *dlnA, double *J, void *hip_stream);
+
+/* Solve (I/hg - J(y)) x = b per cell with the kernels' factorisation, where
+ * hg[c] = h*gamma of the cell; b, x: [c*(N+1) + i] (state order as above). */
+sc_status sc_linsolve(sc_plan *plan, int64_t n, const double *T, const double *p, const double *Y,
+                      int64_t ld, const double *dlnA, const double *hg, const double *b, double *x,
+                      void *hip_stream);
+
+/* Integrate n cells over their own dt[c] at constant p[c].
+ *   in : T0[n], p[n], Y0[N*ld], dt[n], dlnA[R] or NULL,
+ *        h_io[n] or NULL (initial step; the last accepted step is written back)
+ *   out: T1[n], Y1[N*ld] (may alias T0/Y0), cell_status[n],
+ *        n_acc[n], n_rej[n] (NULL allowed)
+ * Options come from the plan (rtol, atol, max_steps, mode, tile, grid). */
+sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0,
+                       int64_t ld, const double *dt, const double *dlnA, double *h_io, double *T1,
+                       double *Y1, int32_t *cell_status, int32_t *n_acc, int32_t *n_rej,
+                       void *hip_stream);
+
+/* Last error message of the calling thread (valid until its next call). */
+const char *sc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,237 @@
+"""stiffchem: batched stiff chemistry integration on MI355X.
+
+Thin ctypes binding of libstiffchem.so (C ABI in include/stiffchem.h).  It
+only marshals arguments: every step of the integration runs in the HIP
+kernels.  PyTorch supplies device memory and the stream; arrays are torch
+tensors on the plan's device:
+
+* ``T``, ``p``, ``dt``: float64 [n]
+* ``Y``: float64 [N, n] (species-major, so ``Y[k]`` is species k of every
+  cell, matching the library's ``Y[k*ld + c]`` with ld = n)
+
+If the shared library is missing this module raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libstiffchem.so")
+
+SC_OK, SC_EINVAL, SC_EPARSE, SC_ENOMEM, SC_EHIP, SC_EUNSUPPORTED, SC_EBUDGET = 0, -1, -2, -3, -4, -5, -6
+CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_BAD_INPUT = range(5)
+MODES = {"plain": 0, "persistent": 1}
+
+
+class StiffchemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"stiffchem error {code}: {msg}")
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32),
+                ("mode", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32),
+                ("order", C.c_int32), ("reserved", C.c_int32)]
+
+
+class MechInfo(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n_species", "n_reactions", "n_third_body", "n_troe",
+                                         "n_elements", "n_state", "n_padded", "nnz_jac", "nnz_lu",
+                                         "n_stages", "rhs_evals_per_step", "exp_per_rhs")] + \
+               [(n, C.c_int64) for n in ("flops_rhs", "flops_jac", "flops_lu", "flops_solve",
+                                         "flops_step")]
+
+
+_lib = None
+_P = C.c_void_p
+_I64 = C.c_int64
+
+
+def lib():
+    """Load the in-tree libstiffchem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"{LIBPATH} is missing: build it with paper_2311_14941_amd.build.build()")
+        L = C.CDLL(LIBPATH)
+        L.sc_last_error.restype = C.c_char_p
+        L.sc_default_options.argtypes = [C.POINTER(Options)]
+        L.sc_mech_load.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(_P)]
+        L.sc_mech_info_get.argtypes = [_P, C.POINTER(MechInfo)]
+        L.sc_species_index.argtypes = [_P, C.c_char_p, C.POINTER(C.c_int32)]
+        L.sc_mech_free.argtypes = [_P]
+        L.sc_mech_free.restype = None
+        L.sc_plan_create.argtypes = [_P, C.c_int, C.POINTER(Options), C.POINTER(_P)]
+        L.sc_plan_free.argtypes = [_P]
+        L.sc_plan_free.restype = None
+        L.sc_rhs.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P]
+        L.sc_jacobian.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P]
+        L.sc_linsolve.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P]
+        L.sc_integrate.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        for f in ("sc_mech_load", "sc_mech_info_get", "sc_species_index", "sc_plan_create", "sc_rhs",
+                  "sc_jacobian", "sc_linsolve", "sc_integrate"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != SC_OK:
+        raise StiffchemError(rc, lib().sc_last_error().decode())
+    return rc
+
+
+def last_error() -> str:
+    return lib().sc_last_error().decode()
+
+
+class Mechanism:
+    """A parsed and compiled mechanism (host side)."""
+
+    def __init__(self, text: str):
+        h = _P()
+        b = text.encode()
+        _check(lib().sc_mech_load(b, len(b), C.byref(h)))
+        self._h = h
+        info = MechInfo()
+        _check(lib().sc_mech_info_get(h, C.byref(info)))
+        self.info = {n: getattr(info, n) for n, _ in MechInfo._fields_}
+        self.N = self.info["n_species"]
+        self.R = self.info["n_reactions"]
+
+    @classmethod
+    def load(cls, path):
+        with open(path) as f:
+            return cls(f.read())
+
+    def species_index(self, name: str) -> int:
+        k = C.c_int32()
+        _check(lib().sc_species_index(self._h, name.encode(), C.byref(k)))
+        return k.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.sc_mech_free(h)
+            self._h = None
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(torch, device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """A mechanism on one device with integration options."""
+
+    def __init__(self, mech: Mechanism, device: int = 0, rtol=1e-6, atol=1e-12, max_steps=100000,
+                 mode="plain", tile=1, grid=0):
+        import torch
+        self.torch = torch
+        self.mech = mech
+        self.device = device
+        opt = Options()
+        lib().sc_default_options(C.byref(opt))
+        opt.rtol, opt.atol, opt.max_steps = rtol, atol, max_steps
+        opt.mode, opt.tile, opt.grid = MODES[mode], tile, grid
+        self.options = opt
+        h = _P()
+        _check(lib().sc_plan_create(mech._h, device, C.byref(opt), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.sc_plan_free(h)
+            self._h = None
+
+    # -- argument marshalling ------------------------------------------------
+    def _dev(self, x, dtype=None):
+        t = self.torch
+        dtype = dtype or t.float64
+        x = t.as_tensor(x, dtype=dtype, device=f"cuda:{self.device}")
+        return x.contiguous()
+
+    def _state(self, T, p, Y):
+        T, p, Y = self._dev(T), self._dev(p), self._dev(Y)
+        n = T.shape[0]
+        if p.dim() == 0:
+            p = p.expand(n).contiguous()
+        if Y.shape != (self.mech.N, n):
+            raise ValueError(f"Y must be [N={self.mech.N}, n={n}], got {tuple(Y.shape)}")
+        return T, p, Y, n
+
+    def _dlnA(self, dlnA):
+        if dlnA is None:
+            return None
+        d = self._dev(dlnA)
+        if d.shape != (self.mech.R,):
+            raise ValueError("dlnA must have one entry per reaction")
+        return d
+
+    # -- entry points ----------------------------------------------------------
+    def rhs(self, T, p, Y, dlnA=None):
+        T, p, Y, n = self._state(T, p, Y)
+        d = self._dlnA(dlnA)
+        fT = self.torch.empty_like(T)
+        fY = self.torch.empty_like(Y)
+        _check(lib().sc_rhs(self._h, n, _ptr(T), _ptr(p), _ptr(Y), n, _ptr(d), _ptr(fT), _ptr(fY),
+                            _stream(self.torch, self.device)))
+        return fT, fY
+
+    def jacobian(self, T, p, Y, dlnA=None):
+        """J[c, i, j] = d f_i / d y_j with y = (Y_0..Y_{N-1}, T)."""
+        T, p, Y, n = self._state(T, p, Y)
+        d = self._dlnA(dlnA)
+        m = self.mech.N + 1
+        J = self.torch.empty((n, m, m), dtype=self.torch.float64, device=T.device)
+        _check(lib().sc_jacobian(self._h, n, _ptr(T), _ptr(p), _ptr(Y), n, _ptr(d), _ptr(J),
+                                 _stream(self.torch, self.device)))
+        return J
+
+    def linsolve(self, T, p, Y, hg, b, dlnA=None):
+        """x with (I/hg - J) x = b per cell; b [n, N+1]."""
+        T, p, Y, n = self._state(T, p, Y)
+        d = self._dlnA(dlnA)
+        hg = self._dev(hg)
+        b = self._dev(b)
+        x = self.torch.empty_like(b)
+        _check(lib().sc_linsolve(self._h, n, _ptr(T), _ptr(p), _ptr(Y), n, _ptr(d), _ptr(hg), _ptr(b),
+                                 _ptr(x), _stream(self.torch, self.device)))
+        return x
+
+    def integrate(self, T0, p, Y0, dt, dlnA=None, h=None, out=None):
+        """Integrate every cell over its own dt.  Returns a dict with T, Y,
+        status, n_acc, n_rej and (when h is given) the carried step h."""
+        T0, p, Y0, n = self._state(T0, p, Y0)
+        dt = self._dev(dt)
+        if dt.dim() == 0:
+            dt = dt.expand(n).contiguous()
+        d = self._dlnA(dlnA)
+        hio = None if h is None else self._dev(h).clone()
+        t = self.torch
+        if out is None:
+            out = dict(T=t.empty_like(T0), Y=t.empty_like(Y0),
+                       status=t.empty(n, dtype=t.int32, device=T0.device),
+                       n_acc=t.empty(n, dtype=t.int32, device=T0.device),
+                       n_rej=t.empty(n, dtype=t.int32, device=T0.device))
+        _check(lib().sc_integrate(self._h, n, _ptr(T0), _ptr(p), _ptr(Y0), n, _ptr(dt), _ptr(d),
+                                  _ptr(hio), _ptr(out["T"]), _ptr(out["Y"]), _ptr(out["status"]),
+                                  _ptr(out["n_acc"]), _ptr(out["n_rej"]), _stream(t, self.device)))
+        if hio is not None:
+            out["h"] = hio
+        return out
+
+
+def ensure_built():
+    """Build the library only if it is missing (tests and benchmarks)."""
+    if not os.path.exists(LIBPATH):
+        from . import build as _b
+        _b.build()
+    return LIBPATH

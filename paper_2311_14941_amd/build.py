@@ -1,0 +1,61 @@
+"""Build libstiffchem.so (host compiler + HIP kernels for gfx950) in-tree."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INC = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libstiffchem.so")
+OBJDIR = os.path.join(HERE, "_build")
+SOURCES = ["mech.cpp", "capi.cpp", "kernels.hip"]
+HEADERS = ["mech.hpp", "devmech.hpp"]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = os.environ.get("STIFFCHEM_ARCH", "gfx950")
+FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+         # packed FP32 instructions are kept out of every HIP build
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         f"-I{INC}", f"-I{CSRC}"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("build failed: " + " ".join(cmd))
+
+
+def build(force=True, jobs=3):
+    """Compile every source (in parallel) and link the shared library."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    procs = []
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(OBJDIR, src + ".o")
+        objs.append(obj)
+        path = os.path.join(CSRC, src)
+        deps = [path] + [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(INC, "stiffchem.h")]
+        if not force and os.path.exists(obj) and all(os.path.getmtime(obj) >= os.path.getmtime(d) for d in deps):
+            continue
+        procs.append((subprocess.Popen([HIPCC, *FLAGS, "-c", path, "-o", obj], stdout=subprocess.PIPE,
+                                       stderr=subprocess.PIPE, text=True), src))
+    failed = []
+    for p, src in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out + err)
+            failed.append(src)
+    if failed:
+        raise RuntimeError("build failed: " + ", ".join(failed))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(force="--force" in sys.argv))

@@ -1,0 +1,326 @@
+// C ABI of libstiffchem (declared in include/stiffchem.h).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "devmech.hpp"
+#include "mech.hpp"
+#include "stiffchem.h"
+
+struct sc_mech {
+    sc::Mech m;
+};
+
+struct sc_plan {
+    sc::Mech m;  // private copy: the plan does not depend on the sc_mech's lifetime
+    sc_options opt;
+    int device = 0;
+    int np = 0;
+    scdev::DevMech dm{};
+    std::vector<void *> allocs;
+    unsigned long long *queue = nullptr;
+    int capacity = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+sc_status fail(sc_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+sc_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(SC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+bool upload(sc_plan *p, const std::vector<T> &v, const T **out)
+{
+    size_t bytes = sizeof(T) * (v.empty() ? 1 : v.size());
+    void *d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) return false;
+    p->allocs.push_back(d);
+    if (!v.empty() && hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return false;
+    *out = static_cast<const T *>(d);
+    return true;
+}
+
+void release(sc_plan *p)
+{
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    for (void *d : p->allocs) (void)hipFree(d);
+    p->allocs.clear();
+    (void)hipSetDevice(cur);
+}
+
+struct DeviceGuard {
+    int prev = 0;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    }
+    ~DeviceGuard()
+    {
+        if (ok) (void)hipSetDevice(prev);
+    }
+};
+
+sc_status check_common(sc_plan *plan, int64_t n, int64_t ld, std::initializer_list<const void *> ptrs)
+{
+    if (!plan) return fail(SC_EINVAL, "plan is NULL");
+    if (n < 0) return fail(SC_EINVAL, "n must be >= 0");
+    if (n > INT_MAX) return fail(SC_EINVAL, "n exceeds 2^31-1 cells");
+    if (n == 0) return SC_OK;
+    if (ld < n) return fail(SC_EINVAL, "ld must be >= n");
+    for (const void *q : ptrs)
+        if (!q) return fail(SC_EINVAL, "required array pointer is NULL");
+    return SC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sc_last_error(void) { return g_err.c_str(); }
+
+void sc_default_options(sc_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->rtol = 1e-6;
+    opt->atol = 1e-12;
+    opt->max_steps = 100000;
+    opt->mode = SC_MODE_PLAIN;
+    opt->tile = 1;
+    opt->grid = 0;
+    opt->order = 0;
+}
+
+sc_status sc_mech_load(const char *text, size_t len, sc_mech **out)
+{
+    if (!out) return fail(SC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!text) return fail(SC_EINVAL, "text is NULL");
+    try {
+        auto *h = new sc_mech{sc::load_mechanism(std::string(text, len))};
+        *out = h;
+        return SC_OK;
+    } catch (const sc::Unsupported &e) {
+        return fail(SC_EUNSUPPORTED, e.what());
+    } catch (const sc::ParseError &e) {
+        return fail(SC_EPARSE, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(SC_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(SC_EPARSE, e.what());
+    }
+}
+
+void sc_mech_free(sc_mech *mech) { delete mech; }
+
+sc_status sc_mech_info_get(const sc_mech *mech, sc_mech_info *out)
+{
+    if (!mech || !out) return fail(SC_EINVAL, "NULL argument");
+    const sc::Mech &m = mech->m;
+    std::memset(out, 0, sizeof *out);
+    out->n_species = m.N;
+    out->n_reactions = m.R;
+    out->n_third_body = m.n_third;
+    out->n_troe = m.n_troe;
+    out->n_elements = m.E;
+    out->n_state = m.N + 1;
+    out->n_padded = m.n_padded;
+    out->nnz_jac = m.cnt.nnz_jac;
+    out->nnz_lu = m.cnt.nnz_lu;
+    out->n_stages = 4;
+    out->rhs_evals_per_step = 3;
+    out->exp_per_rhs = m.cnt.exp_per_rhs;
+    out->flops_rhs = m.cnt.flops_rhs;
+    out->flops_jac = m.cnt.flops_jac;
+    out->flops_lu = m.cnt.flops_lu;
+    out->flops_solve = m.cnt.flops_solve;
+    out->flops_step = m.cnt.flops_step;
+    return SC_OK;
+}
+
+sc_status sc_species_index(const sc_mech *mech, const char *name, int32_t *idx)
+{
+    if (!mech || !name || !idx) return fail(SC_EINVAL, "NULL argument");
+    int k = mech->m.species(name);
+    if (k < 0) return fail(SC_EINVAL, std::string("unknown species ") + name);
+    *idx = k;
+    return SC_OK;
+}
+
+sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt, sc_plan **out)
+{
+    if (!out) return fail(SC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!mech) return fail(SC_EINVAL, "mech is NULL");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(SC_EHIP, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(SC_EINVAL, "device index out of range");
+    sc_options o;
+    sc_default_options(&o);
+    if (opt) o = *opt;
+    if (!(o.rtol > 0) || !(o.atol > 0) || !std::isfinite(o.rtol) || !std::isfinite(o.atol))
+        return fail(SC_EINVAL, "rtol and atol must be positive and finite");
+    if (o.max_steps <= 0) return fail(SC_EINVAL, "max_steps must be positive");
+    if (o.mode != SC_MODE_PLAIN && o.mode != SC_MODE_PERSISTENT) return fail(SC_EINVAL, "unknown mode");
+    if (o.tile <= 0) o.tile = 1;
+    if (o.grid < 0) return fail(SC_EINVAL, "grid must be >= 0");
+    DeviceGuard g(device);
+    if (!g.ok) return fail(SC_EHIP, "hipSetDevice failed");
+    sc_plan *p = nullptr;
+    try {
+        p = new sc_plan();
+        p->m = mech->m;
+    } catch (...) {
+        delete p;
+        return fail(SC_ENOMEM, "host allocation failed");
+    }
+    p->opt = o;
+    p->device = device;
+    p->np = p->m.n_padded;
+    const sc::Tables &t = p->m.tab;
+    scdev::DevMech &d = p->dm;
+    d.N = t.N;
+    d.R = t.R;
+    d.nt = t.n_troe;
+    d.Rgas = t.Rgas;
+    d.lnp0R = std::log(t.p0 / t.Rgas);
+    // species table, reaction records, Troe records
+    std::vector<double> spv;
+    spv.reserve(9 * (size_t)t.N);
+    spv.insert(spv.end(), t.W.begin(), t.W.end());
+    spv.insert(spv.end(), t.invW.begin(), t.invW.end());
+    spv.insert(spv.end(), t.nasa.begin(), t.nasa.end());
+    std::vector<scdev::RxRec> rx(t.R);
+    for (int j = 0; j < t.R; ++j) {
+        scdev::RxRec &r = rx[j];
+        std::memset(&r, 0, sizeof r);
+        r.lnA = t.lnA[j];
+        r.b = t.b[j];
+        r.EaR = t.EaR[j];
+        r.kind = t.kind[j];
+        r.nr = t.nr[j];
+        r.np = t.np[j];
+        r.dnu = t.dnu[j];
+        r.neff = t.neff[j];
+        r.tix = t.tix[j];
+        for (int i = 0; i < sc::MAXSIDE; ++i) {
+            r.rsp[i] = t.rsp[i * t.R + j];
+            r.rnu[i] = t.rnu[i * t.R + j];
+            r.psp[i] = t.psp[i * t.R + j];
+            r.pnu[i] = t.pnu[i * t.R + j];
+        }
+        for (int e = 0; e < sc::MAXENH; ++e) {
+            r.esp[e] = t.esp[e * t.R + j];
+            r.eam1[e] = t.eam1[e * t.R + j];
+        }
+    }
+    std::vector<scdev::TroeRec> tr(t.n_troe > 0 ? t.n_troe : 1);
+    for (int k = 0; k < t.n_troe; ++k) {
+        const int nt = t.n_troe;
+        tr[k] = scdev::TroeRec{t.troe[0 * nt + k], t.troe[1 * nt + k], t.troe[2 * nt + k], t.troe[3 * nt + k],
+                               t.troe[4 * nt + k], t.troe[5 * nt + k], t.troe[6 * nt + k], 0.0};
+    }
+    bool ok = upload(p, spv, &d.sp) && upload(p, rx, &d.rx) && upload(p, tr, &d.troe);
+    if (ok) {
+        void *q = nullptr;
+        ok = hipMalloc(&q, sizeof(unsigned long long)) == hipSuccess;
+        if (ok) {
+            p->allocs.push_back(q);
+            p->queue = static_cast<unsigned long long *>(q);
+        }
+    }
+    if (!ok) {
+        release(p);
+        delete p;
+        return fail(SC_ENOMEM, "device allocation/upload failed");
+    }
+    p->capacity = scdev::persistent_capacity(p->np, device);
+    *out = p;
+    return SC_OK;
+}
+
+void sc_plan_free(sc_plan *plan)
+{
+    if (!plan) return;
+    release(plan);
+    delete plan;
+}
+
+sc_status sc_rhs(sc_plan *plan, int64_t n, const double *T, const double *p, const double *Y, int64_t ld,
+                 const double *dlnA, double *fT, double *fY, void *stream)
+{
+    sc_status s = check_common(plan, n, ld, {T, p, Y, fT, fY});
+    if (s != SC_OK || n == 0) return s;
+    DeviceGuard g(plan->device);
+    hipError_t e = scdev::launch_rhs(plan->np, plan->dm, n, T, p, Y, ld, dlnA, fT, fY, (hipStream_t)stream);
+    return e == hipSuccess ? SC_OK : hip_fail(e, "rhs launch");
+}
+
+sc_status sc_jacobian(sc_plan *plan, int64_t n, const double *T, const double *p, const double *Y, int64_t ld,
+                      const double *dlnA, double *J, void *stream)
+{
+    sc_status s = check_common(plan, n, ld, {T, p, Y, J});
+    if (s != SC_OK || n == 0) return s;
+    DeviceGuard g(plan->device);
+    hipError_t e = scdev::launch_jac(plan->np, plan->dm, n, T, p, Y, ld, dlnA, J, (hipStream_t)stream);
+    return e == hipSuccess ? SC_OK : hip_fail(e, "jacobian launch");
+}
+
+sc_status sc_linsolve(sc_plan *plan, int64_t n, const double *T, const double *p, const double *Y, int64_t ld,
+                      const double *dlnA, const double *hg, const double *b, double *x, void *stream)
+{
+    sc_status s = check_common(plan, n, ld, {T, p, Y, hg, b, x});
+    if (s != SC_OK || n == 0) return s;
+    DeviceGuard g(plan->device);
+    hipError_t e =
+        scdev::launch_linsolve(plan->np, plan->dm, n, T, p, Y, ld, dlnA, hg, b, x, (hipStream_t)stream);
+    return e == hipSuccess ? SC_OK : hip_fail(e, "linsolve launch");
+}
+
+sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0, int64_t ld,
+                       const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
+                       int32_t *cell_status, int32_t *n_acc, int32_t *n_rej, void *stream)
+{
+    sc_status s = check_common(plan, n, ld, {T0, p, Y0, dt, T1, Y1, cell_status});
+    if (s != SC_OK || n == 0) return s;
+    DeviceGuard g(plan->device);
+    scdev::Opts o{plan->opt.rtol, plan->opt.atol, plan->opt.max_steps};
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (plan->opt.mode == SC_MODE_PERSISTENT) {
+        const int tile = plan->opt.tile;
+        int64_t tiles = (n + tile - 1) / tile;
+        int grid = plan->opt.grid > 0 ? plan->opt.grid : plan->capacity;
+        if (grid <= 0) grid = 1;
+        if (grid > tiles) grid = (int)tiles;
+        e = scdev::launch_zero_u64(plan->queue, st);
+        if (e == hipSuccess)
+            e = scdev::launch_integrate_persistent(plan->np, plan->dm, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1,
+                                                   Y1, cell_status, n_acc, n_rej, plan->queue, nullptr, tile,
+                                                   grid, st);
+    } else {
+        e = scdev::launch_integrate(plan->np, plan->dm, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, cell_status,
+                                    n_acc, n_rej, st);
+    }
+    return e == hipSuccess ? SC_OK : hip_fail(e, "integrate launch");
+}
+
+}  // extern "C"

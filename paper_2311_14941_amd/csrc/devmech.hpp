@@ -1,0 +1,70 @@
+// Device view of a compiled mechanism and the launch interface of the
+// kernels (shared by kernels.hip and capi.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mech.hpp"
+#include "stiffchem.h"
+
+namespace scdev {
+
+// One reaction's parameters, read by the lane that handles the reaction
+// (144 bytes; the 64 lanes of a pass read 64 consecutive records).
+struct RxRec {
+    double lnA, b, EaR;            // SI ln A (incl. the cgs conversion), b, Ea/R
+    double eam1[sc::MAXENH];       // alpha - 1 of the enhanced third-body species
+    int32_t kind, nr, np, dnu, neff, tix;
+    int32_t rsp[sc::MAXSIDE], rnu[sc::MAXSIDE], psp[sc::MAXSIDE], pnu[sc::MAXSIDE];
+    int32_t esp[sc::MAXENH];
+};
+static_assert(sizeof(RxRec) % 16 == 0, "record size");
+
+struct TroeRec {
+    double lnA0, b0, Ea0R, a, iT3, iT1, T2, pad;
+};
+
+// A compiled mechanism on the device: species table sp = W[N] invW[N]
+// nasa[7][N] (species index fastest), one record per reaction and per Troe
+// reaction.  Three base pointers keep the kernels' scalar-register footprint
+// small.
+struct DevMech {
+    int N, R, nt;
+    double Rgas, lnp0R;  // lnp0R = ln(p0 / Rgas)
+    const double *sp;
+    const RxRec *rx;
+    const TroeRec *troe;
+
+    __host__ __device__ const double *W() const { return sp; }
+    __host__ __device__ const double *invW() const { return sp + N; }
+    __host__ __device__ const double *nasa() const { return sp + 2 * N; }  // [c*N + k]
+};
+
+struct Opts {
+    double rtol, atol;
+    int max_steps;
+};
+
+hipError_t launch_rhs(int np, const DevMech &m, int64_t n, const double *T, const double *p, const double *Y,
+                      int64_t ld, const double *dlnA, double *fT, double *fY, hipStream_t s);
+hipError_t launch_jac(int np, const DevMech &m, int64_t n, const double *T, const double *p, const double *Y,
+                      int64_t ld, const double *dlnA, double *J, hipStream_t s);
+hipError_t launch_linsolve(int np, const DevMech &m, int64_t n, const double *T, const double *p,
+                           const double *Y, int64_t ld, const double *dlnA, const double *hg, const double *b,
+                           double *x, hipStream_t s);
+hipError_t launch_integrate(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0,
+                            const double *p, const double *Y0, int64_t ld, const double *dt, const double *dlnA,
+                            double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr,
+                            hipStream_t s);
+hipError_t launch_integrate_persistent(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0,
+                                       const double *p, const double *Y0, int64_t ld, const double *dt,
+                                       const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st,
+                                       int32_t *na, int32_t *nr, unsigned long long *queue,
+                                       const int32_t *perm, int tile, int grid, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
+int persistent_capacity(int np, int device);
+size_t lds_bytes_for(int np);
+
+}  // namespace scdev

@@ -1,0 +1,306 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (spec bar): integrated T and mass fractions above 1e-8 to
+relative 1e-6, mass fractions below to absolute 1e-12, against converged
+oracle references (tests/golden).  Right-hand side and Jacobian: element-wise
+against the oracle's definition and its complex-step Jacobian, scaled by the
+gross forward and reverse rates that feed each component (their roundoff is
+what two correct implementations can differ by)."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a HIP device"
+    return t
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import paper_2311_14941_amd as m
+    m.ensure_built()
+    return m
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    from oracle import oracle as o
+    return o
+
+
+_CELLS = {}
+
+
+def cells(key):
+    from synth.cells import make_cells
+    if key not in _CELLS:
+        _CELLS[key] = make_cells(key)
+    return _CELLS[key]
+
+
+def to_gpu(torch, c, idx):
+    d = "cuda:0"
+    T = torch.tensor(c["T"][idx], dtype=torch.float64, device=d)
+    p = torch.tensor(c["p"][idx], dtype=torch.float64, device=d)
+    Y = torch.tensor(np.ascontiguousarray(c["Y"][idx].T), dtype=torch.float64, device=d)
+    dt = torch.tensor(c["dt"][idx], dtype=torch.float64, device=d)
+    return T, p, Y, dt
+
+
+def parity_excess(T, Y, Tref, Yref):
+    """Per cell: max over components of |error| / tolerance (<= 1 passes)."""
+    eT = np.abs(T - Tref) / (1e-6 * np.abs(Tref))
+    big = np.abs(Yref) > 1e-8
+    eY = np.where(big, np.abs(Y - Yref) / (1e-6 * np.abs(Yref) + 1e-300), np.abs(Y - Yref) / 1e-12)
+    return np.maximum(eT, eY.max(1))
+
+
+def gross_scale(o, mech, T, p, Y):
+    """Per component, sum_j |nu_ij| (|forward| + |reverse| rate) mapped to dY/dt
+    and dT/dt units: the size of the terms whose roundoff the RHS carries."""
+    kf, kr, q, wdot, aux = o.rates(T, p, Y)
+    rho, cp = aux[0], aux[1]
+    W = mech.molar_masses()
+    C = rho * Y / W
+    g = np.zeros(mech.n_species)
+    for j, r in enumerate(mech.reactions):
+        pf = np.prod([C[k] ** v for k, v in r.reac])
+        pr = np.prod([C[k] ** v for k, v in r.prod])
+        M = 1.0
+        if r.kind == "third":
+            M = sum(r.eff.get(k, 1.0) * C[k] for k in range(mech.n_species))
+        gross = (abs(kf[j] * pf) + abs(kr[j] * pr)) * M
+        for k, v in r.reac + r.prod:
+            g[k] += v * gross
+    sY = W * g / rho
+    h = o.thermo(T)[1] * 8.314462618 * T
+    sT = np.sum(np.abs(h) * g) / (rho * cp)
+    return sY, sT
+
+
+@pytest.mark.parametrize("key,ncell", [("C1", 256), ("C2", 96)])
+def test_rhs_parity(torch, sc, oracle_mod, key, ncell):
+    c = cells(key)
+    mech = c["mech"]
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(c["T"].size, ncell, replace=False))
+    plan = sc.Plan(sc.Mechanism(mech.to_text()))
+    T, p, Y, _ = to_gpu(torch, c, idx)
+    fT, fY = plan.rhs(T, p, Y)
+    fT, fY = fT.cpu().numpy(), fY.cpu().numpy().T
+    o = oracle_mod.Oracle(mech.to_text())
+    worst = 0.0
+    for n, i in enumerate(idx):
+        y = np.append(c["Y"][i], c["T"][i])
+        f = o.rhs(y, c["p"][i])
+        sY, sT = gross_scale(o, mech, c["T"][i], c["p"][i], c["Y"][i])
+        eY = np.abs(fY[n] - f[:-1]) / (sY + 1e-300)
+        eT = abs(fT[n] - f[-1]) / (sT + 1e-300)
+        worst = max(worst, eY.max(), eT)
+    assert worst < 1e-12, worst
+
+
+@pytest.mark.parametrize("key,ncell", [("C1", 64), ("C2", 48)])
+def test_jacobian_parity(torch, sc, oracle_mod, key, ncell):
+    """Analytical J (device) against the oracle's complex-step J."""
+    c = cells(key)
+    mech = c["mech"]
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(c["T"].size, ncell, replace=False))
+    plan = sc.Plan(sc.Mechanism(mech.to_text()))
+    T, p, Y, _ = to_gpu(torch, c, idx)
+    J = plan.jacobian(T, p, Y).cpu().numpy()
+    o = oracle_mod.Oracle(mech.to_text())
+    worst = 0.0
+    for n, i in enumerate(idx):
+        y = np.append(c["Y"][i], c["T"][i])
+        Jc = o.jac_cs(y, c["p"][i])
+        row = np.abs(Jc).max(1, keepdims=True) + 1e-300
+        err = np.abs(J[n] - Jc) / (1e-8 * np.abs(Jc) + 1e-12 * row)
+        worst = max(worst, err.max())
+    assert worst <= 1.0, worst
+
+
+def test_linsolve_parity(torch, sc, oracle_mod):
+    """(I/hg - J) x = b with the kernel's pivot-free LU against a dense
+    partial-pivoting solve of the complex-step matrix."""
+    c = cells("C2")
+    mech = c["mech"]
+    idx = np.arange(0, 4096, 128)
+    plan = sc.Plan(sc.Mechanism(mech.to_text()))
+    T, p, Y, _ = to_gpu(torch, c, idx)
+    n = idx.size
+    m = mech.n_species + 1
+    rng = np.random.default_rng(2)
+    b = rng.normal(size=(n, m))
+    o = oracle_mod.Oracle(mech.to_text())
+    for hg in (1e-9, 1e-6, 1e-3):
+        x = plan.linsolve(T, p, Y, np.full(n, hg), b).cpu().numpy()
+        for k, i in enumerate(idx):
+            Jc = o.jac_cs(np.append(c["Y"][i], c["T"][i]), c["p"][i])
+            A = np.eye(m) / hg - Jc
+            ref = np.linalg.solve(A, b[k])
+            res = np.abs(A @ x[k] - b[k]).max() / (np.abs(A).max() * np.abs(x[k]).max() + np.abs(b[k]).max())
+            assert res < 1e-12, (hg, i, res)
+            assert np.allclose(x[k], ref, rtol=1e-7, atol=1e-9 * np.abs(ref).max()), (hg, i)
+
+
+def _golden(name):
+    return np.load(os.path.join(HERE, "golden", name))
+
+
+@pytest.mark.parametrize("key,golden", [("C1", "c1_ref.npz"), ("C2", "c2_ref.npz")])
+def test_integrate_tight_tolerance_parity(torch, sc, key, golden):
+    """Gate G1: at rtol 1e-10 / atol 1e-16 every cell meets the parity bar
+    against the converged oracle reference."""
+    c = cells(key)
+    g = _golden(golden)
+    idx = g["idx"]
+    plan = sc.Plan(sc.Mechanism(c["mech"].to_text()), rtol=1e-10, atol=1e-16, max_steps=200000)
+    T, p, Y, dt = to_gpu(torch, c, idx)
+    r = plan.integrate(T, p, Y, dt)
+    st = r["status"].cpu().numpy()
+    assert np.all(st == 0), np.bincount(st)
+    ex = parity_excess(r["T"].cpu().numpy(), r["Y"].cpu().numpy().T, g["T"], g["Y"])
+    print(f"{key}: worst parity excess {ex.max():.3g} (<= 1 passes)")
+    assert np.all(ex <= 1.0), (ex.max(), idx[np.argmax(ex)])
+
+
+@pytest.mark.parametrize("key,golden", [("C1", "c1_ref.npz"), ("C2", "c2_ref.npz")])
+def test_integrate_production_tolerance(torch, sc, key, golden):
+    """Gate G2 (reported): at the workload tolerance rtol 1e-6 / atol 1e-12
+    the pass fraction of the literal bar; the test requires every cell to
+    finish and the error to stay within the controller's 100x rtol band."""
+    c = cells(key)
+    g = _golden(golden)
+    idx = g["idx"]
+    plan = sc.Plan(sc.Mechanism(c["mech"].to_text()), rtol=1e-6, atol=1e-12)
+    T, p, Y, dt = to_gpu(torch, c, idx)
+    r = plan.integrate(T, p, Y, dt)
+    st = r["status"].cpu().numpy()
+    assert np.all(st == 0)
+    Tg, Yg = r["T"].cpu().numpy(), r["Y"].cpu().numpy().T
+    ex = parity_excess(Tg, Yg, g["T"], g["Y"])
+    print(f"{key}: G2 pass fraction {np.mean(ex <= 1):.3f}, worst excess {ex.max():.3g}")
+    assert np.all(np.abs(Tg - g["T"]) <= 1e-4 * g["T"])
+
+
+def test_conservation(torch, sc):
+    """Sum of mass fractions and element mass fractions are linear invariants
+    of the method: conserved to roundoff."""
+    c = cells("C2")
+    mech = c["mech"]
+    idx = np.arange(0, 65536, 97)[:512]
+    plan = sc.Plan(sc.Mechanism(mech.to_text()))
+    T, p, Y, dt = to_gpu(torch, c, idx)
+    r = plan.integrate(T, p, Y, dt)
+    assert np.all(r["status"].cpu().numpy() == 0)
+    Y1 = r["Y"].cpu().numpy().T
+    Y0 = c["Y"][idx]
+    assert np.abs(Y1.sum(1) - Y0.sum(1)).max() < 1e-13
+    A = mech.element_matrix() / mech.molar_masses()[None, :]
+    e0, e1 = Y0 @ A.T, Y1 @ A.T
+    assert np.abs(e1 - e0).max() < 1e-12 * np.abs(e0).max()
+
+
+def test_stability_function_isomer(torch, sc, oracle_mod):
+    """One step of the method on the linear A <=> B problem multiplies the
+    deviation from equilibrium by R(-k h), R from the tableau."""
+    from paper_2311_14941_amd.tableau import stability
+    from synth.mechgen import isomer_mechanism
+    mech = isomer_mechanism(log10A=9.0, b=0.0, Ea=40e3, ds_R=0.7)
+    o = oracle_mod.Oracle(mech.to_text())
+    Tc, pc = 1000.0, 101325.0
+    kf, kr, *_ = o.rates(Tc, pc, [0.5, 0.5])
+    k = kf[0] + kr[0]
+    Yeq = 1.0 / (1.0 + np.exp(0.7))
+    plan = sc.Plan(sc.Mechanism(mech.to_text()), rtol=1e6, atol=1e6)  # accept the first step
+    for z in (0.01, 0.5, 3.0, 50.0, 1e4):
+        h = z / k
+        T = torch.tensor([Tc], dtype=torch.float64, device="cuda:0")
+        Y = torch.tensor([[0.9], [0.1]], dtype=torch.float64, device="cuda:0")
+        r = plan.integrate(T, pc, Y, torch.tensor([h], dtype=torch.float64, device="cuda:0"))
+        assert int(r["n_acc"][0]) == 1 and int(r["n_rej"][0]) == 0
+        got = (r["Y"][0, 0].item() - Yeq) / (0.9 - Yeq)
+        want = stability(-z)[0].real
+        assert abs(got - want) < 1e-12, (z, got, want)
+
+
+def test_edge_cases(torch, sc):
+    c = cells("C1")
+    mech = sc.Mechanism(c["mech"].to_text())
+    plan = sc.Plan(mech)
+    # empty batch: no launch, no error
+    T, p, Y, dt = to_gpu(torch, c, np.arange(0))
+    r = plan.integrate(T, p, Y, dt)
+    assert r["T"].numel() == 0
+    # ragged sizes give the same per-cell answers as a large batch
+    big = plan.integrate(*to_gpu(torch, c, np.arange(200)))
+    for n in (1, 63, 65, 129):
+        rr = plan.integrate(*to_gpu(torch, c, np.arange(n)))
+        assert torch.equal(rr["T"], big["T"][:n])
+        assert torch.equal(rr["Y"], big["Y"][:, :n])
+    # bad inputs become per-cell status codes; the rest of the batch is fine
+    idx = np.arange(8)
+    T, p, Y, dt = to_gpu(torch, c, idx)
+    T[1] = float("nan")
+    T[2] = -5.0
+    p[3] = 0.0
+    dt[4] = -1e-5
+    Y[0, 5] = float("inf")
+    dt[6] = 0.0
+    r = plan.integrate(T, p, Y, dt)
+    st = r["status"].cpu().numpy()
+    assert list(st[[1, 2, 3, 4, 5]]) == [4, 4, 4, 4, 4]
+    assert st[0] == 0 and st[6] == 0 and st[7] == 0
+    assert torch.equal(r["Y"][:, 6], Y[:, 6]) and r["T"][6] == T[6]  # dt = 0: unchanged
+    # max_steps: a step budget of 1 stops cells that need more
+    plan1 = sc.Plan(mech, max_steps=1)
+    r = plan1.integrate(*to_gpu(torch, c, np.arange(16)))
+    assert np.any(r["status"].cpu().numpy() == 1)
+    # argument errors are synchronous and leave no launch behind
+    with pytest.raises(ValueError):
+        plan.integrate(T, p, Y[:, :4], dt)
+    L = sc.lib()
+    rc = L.sc_integrate(plan._h, 8, None, None, None, 8, None, None, None, None, None, None, None, None, None)
+    assert rc == sc.SC_EINVAL and "NULL" in sc.last_error()
+    rc = L.sc_integrate(plan._h, -1, None, None, None, 8, None, None, None, None, None, None, None, None, None)
+    assert rc == sc.SC_EINVAL
+
+
+def test_determinism_and_persistent_equal(torch, sc):
+    """Two plain launches, and the persistent queue, give bitwise equal results."""
+    c = cells("C2")
+    mech = sc.Mechanism(c["mech"].to_text())
+    idx = np.arange(0, 65536, 41)[:1000]
+    args = to_gpu(torch, c, idx)
+    a = sc.Plan(mech).integrate(*args)
+    b = sc.Plan(mech).integrate(*args)
+    pq = sc.Plan(mech, mode="persistent", tile=2).integrate(*args)
+    for k in ("T", "Y", "status", "n_acc", "n_rej"):
+        assert torch.equal(a[k], b[k]), k
+        assert torch.equal(a[k], pq[k]), k
+
+
+def test_h_carry(torch, sc):
+    """Chained substeps with the carried step size: integrating dt in two
+    halves with h carried matches the tolerance-level answer of one call."""
+    c = cells("C2")
+    mech = sc.Mechanism(c["mech"].to_text())
+    idx = np.arange(0, 65536, 1024)
+    T, p, Y, dt = to_gpu(torch, c, idx)
+    plan = sc.Plan(mech, rtol=1e-9, atol=1e-15)
+    one = plan.integrate(T, p, Y, dt)
+    h = torch.zeros_like(T)
+    half = plan.integrate(T, p, Y, dt / 2, h=h)
+    two = plan.integrate(half["T"], p, half["Y"], dt / 2, h=half["h"])
+    assert torch.all(half["h"] > 0)
+    assert torch.allclose(one["T"], two["T"], rtol=1e-6)
