@@ -30,7 +30,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cells, budget_s=20.0):
+def cpu_baseline(cells, budget_s=15.0):
     """The oracle (plain dense Radau IIA, FD Jacobian) at the production
     tolerance on a stratified sample of the same batch, all host threads."""
     from oracle.oracle import Oracle, max_threads
@@ -38,7 +38,7 @@ def cpu_baseline(cells, budget_s=20.0):
     o = Oracle(cells["mech"].to_text())
     threads = max_threads()
     done, t_used, per = 0, 0.0, 8
-    sample = stratified(cells["cls"], 64, seed=5)
+    sample = stratified(cells["cls"], 2048, seed=5)
     rng = np.random.default_rng(5)
     sample = rng.permutation(sample)
     # warm-up on a few cells, then time batches until the budget is used

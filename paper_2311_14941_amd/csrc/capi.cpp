@@ -1,7 +1,9 @@
 // C ABI of libstiffchem (declared in include/stiffchem.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -208,9 +210,19 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
     spv.insert(spv.end(), t.W.begin(), t.W.end());
     spv.insert(spv.end(), t.invW.begin(), t.invW.end());
     spv.insert(spv.end(), t.nasa.begin(), t.nasa.end());
+    // execution order: plain, third-body, Troe; then by side sizes, so that
+    // the 64 reactions of a pass take the same branches (the original index
+    // is kept for per-reaction inputs)
+    std::vector<int> order(t.R);
+    for (int j = 0; j < t.R; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        auto key = [&](int j) { return std::make_tuple(t.kind[j], t.neff[j] > 0, t.nr[j] + t.np[j]); };
+        return key(x) < key(y);
+    });
     std::vector<scdev::RxRec> rx(t.R);
-    for (int j = 0; j < t.R; ++j) {
-        scdev::RxRec &r = rx[j];
+    for (int q = 0; q < t.R; ++q) {
+        const int j = order[q];
+        scdev::RxRec &r = rx[q];
         std::memset(&r, 0, sizeof r);
         r.lnA = t.lnA[j];
         r.b = t.b[j];
@@ -231,6 +243,7 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
             r.esp[e] = t.esp[e * t.R + j];
             r.eam1[e] = t.eam1[e * t.R + j];
         }
+        r.orig = j;
     }
     std::vector<scdev::TroeRec> tr(t.n_troe > 0 ? t.n_troe : 1);
     for (int k = 0; k < t.n_troe; ++k) {

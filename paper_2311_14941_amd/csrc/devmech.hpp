@@ -12,13 +12,16 @@
 namespace scdev {
 
 // One reaction's parameters, read by the lane that handles the reaction
-// (144 bytes; the 64 lanes of a pass read 64 consecutive records).
+// (160 bytes; the 64 lanes of a pass read 64 consecutive records).  Records
+// are in the compiler's execution order (by kind, then side sizes).
 struct RxRec {
     double lnA, b, EaR;            // SI ln A (incl. the cgs conversion), b, Ea/R
     double eam1[sc::MAXENH];       // alpha - 1 of the enhanced third-body species
     int32_t kind, nr, np, dnu, neff, tix;
     int32_t rsp[sc::MAXSIDE], rnu[sc::MAXSIDE], psp[sc::MAXSIDE], pnu[sc::MAXSIDE];
     int32_t esp[sc::MAXENH];
+    int32_t orig;  // index of the reaction in the mechanism text (for dlnA)
+    int32_t pad[3];
 };
 static_assert(sizeof(RxRec) % 16 == 0, "record size");
 

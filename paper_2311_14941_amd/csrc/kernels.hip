@@ -24,17 +24,28 @@
 namespace scdev {
 
 // ---------------------------------------------------------------------------
-// Rosenbrock tableau (transformed form; derivation in tableau.py):
-// 4 stages, order 3, embedded order 2, gamma = 1/2, stiffly accurate.
+// Rosenbrock tableau (transformed form; derivation in tableau.py, ros4()):
+// 4 stages, order 4, L-stable, embedded order 3; stage 4 is evaluated at the
+// stage-3 point, so a step costs 3 function evaluations (one of them in the
+// Jacobian pass), 1 factorisation and 4 solves.
 // ---------------------------------------------------------------------------
 constexpr int NS = 4;
-constexpr double GAM = 0.5;
-__constant__ double TA[NS][NS] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {2, 0, 0, 0}, {2, 0, 1, 0}};
-__constant__ double TC[NS][NS] = {{0, 0, 0, 0}, {4, 0, 0, 0}, {1, -1, 0, 0}, {1, -1, -8.0 / 3.0, 0}};
-__constant__ double TM[NS] = {2, 0, 1, 1};
-__constant__ double TE[NS] = {0, 0, 0, 1};  // m - mhat
-__constant__ int TSAME[NS] = {1, 1, 0, 0};  // stage evaluates f at y (reuses f0)
-constexpr double ERR_EXP = 1.0 / 3.0;       // 1/(embedded order + 1)
+constexpr double GAM = 0.572816062482135;
+__constant__ double TA[NS][NS] = {{0.0, 0.0, 0.0, 0.0},
+                                  {1.0474566606950075, 0.0, 0.0, 0.0},
+                                  {1.5266834054578882, 0.49110997987229194, 0.0, 0.0},
+                                  {1.5266834054578882, 0.49110997987229194, 0.0, 0.0}};
+__constant__ double TC[NS][NS] = {{0.0, 0.0, 0.0, 0.0},
+                                  {-2.8287104387961546, 0.0, 0.0, 0.0},
+                                  {-1.1423273772481277, 0.9544101947030211, 0.0, 0.0},
+                                  {-3.972521690537523, -0.6901523982223108, -1.548869644699513, 0.0}};
+__constant__ double TM[NS] = {2.326763557172835, -0.7953731300411474, 1.6632540048577067, 1.0474566606950075};
+__constant__ double TE[NS] = {0.4092508278871161, -1.0795845833425672, 0.9649495643943683,
+                              1.0474566606950078};  // m - mhat
+// function value of a stage: 0 = f(y) from the Jacobian pass, -1 = evaluate,
+// k > 0 = reuse the value evaluated at stage k (same point)
+__constant__ int TREUSE[NS] = {0, -1, -1, 2};
+constexpr double ERR_EXP = 1.0 / 4.0;  // 1/(embedded order + 1)
 
 constexpr int WAVE = 64;
 // LDS loads issued ahead per group in the unrolled row/solve loops; bounds
@@ -327,7 +338,7 @@ __device__ double rhs(const DevMech &m, double *lds, double y, double p, const d
     wave_sync();
 #pragma unroll 1
     for (int j = lane; j < R; j += WAVE) {
-        const double dl = dlnA ? dlnA[j] : 0.0;
+        const double dl = dlnA ? dlnA[m.rx[j].orig] : 0.0;
         const RxOut o = reaction<false>(m, lds, j, x, dl, Lds<NP>::C, Lds<NP>::G, Lds<NP>::H);
         scatter<NP, false>(m, lds, j, o, 0.0);
     }
@@ -367,7 +378,7 @@ __device__ double rhs_jac(const DevMech &m, double *lds, double y, double p, con
     const double RT = m.Rgas * x.T;
 #pragma unroll 1
     for (int j = lane; j < R; j += WAVE) {
-        const double dl = dlnA ? dlnA[j] : 0.0;
+        const double dl = dlnA ? dlnA[m.rx[j].orig] : 0.0;
         const RxOut o = reaction<true>(m, lds, j, x, dl, Lds<NP>::C, Lds<NP>::G, Lds<NP>::H);
         scatter<NP, true>(m, lds, j, o, o.dH * RT);
     }
@@ -624,15 +635,20 @@ __device__ void integrate_cell(const DevMech &m, const Opts &o, double *lds, int
             if (t + hc >= dt) { hc = dt - t; last = true; }
             const double dinv = factor_matrix<NP>(m, lds, rc, lane, 1.0 / (GAM * hc));
             const double ih = 1.0 / hc;
+            double flast = f0;
 #pragma unroll 1
             for (int i = 0; i < NS; ++i) {
                 double fi;
-                if (TSAME[i]) {
+                const int reuse = TREUSE[i];
+                if (reuse == 0) {
                     fi = f0;
+                } else if (reuse > 0) {
+                    fi = flast;  // the stage it names is the last one evaluated
                 } else {
                     double ys = y;
                     for (int j = 0; j < i; ++j) ys += TA[i][j] * U[j * WAVE + lane];
                     fi = rhs<NP>(m, lds, ys, p, dlnA, lane);
+                    flast = fi;
                 }
                 for (int j = 0; j < i; ++j) fi += (TC[i][j] * ih) * U[j * WAVE + lane];
                 if (lane >= n) fi = 0.0;

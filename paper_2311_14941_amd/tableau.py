@@ -1,5 +1,7 @@
-"""Rosenbrock tableau used by the device integrator, derived here from the
-order conditions rather than taken from any code.
+"""Rosenbrock tableaus, derived here from the order conditions rather than
+taken from any code: an order-3 method (``tableau()``, kept as a reference
+and for tests) and the order-4 method the device integrator uses
+(``ros4()``).
 
 The paper's solver is an unnamed "standard" stiff ODE integrator (Sec. 2.5)
 fed by a sparse analytical Jacobian; this library uses a linearly implicit
@@ -99,9 +101,89 @@ def _inv_lower(L):
     return X
 
 
+# ---------------------------------------------------------------------------
+# Order 4 (the device method): 4 stages, 3 function evaluations per step.
+#
+# Choices: gamma = the largest root in (0.2, 0.6) of the z^4 coefficient of
+# trunc_4[(1 - gamma z)^4 e^z] (this makes R(inf) = 0: L-stability for a
+# 4-stage order-4 method); alpha_4j = alpha_3j so stage 4 reuses the function
+# value of stage 3; the embedded method uses stages 1-3 only (bhat_4 = 0) and
+# has order 3.  With the order-4 conditions (order-3 set above plus
+#   sum b_i alpha_i^3 = 1/4,  sum b_i alpha_i alpha_ij beta'_j = 1/8 - gamma/3,
+#   sum b_i beta_ij alpha_j^2 = 1/12 - gamma/3,
+#   sum b_i beta_ij beta_jk beta'_k = 1/24 - gamma/2 + 3 gamma^2/2 - gamma^3)
+# the system reduces to closed forms (see ros4()): the quadrature conditions
+# give b_2 and b_3 + b_4, the b-alpha-alpha-beta' condition gives alpha_32,
+# the embedded order-3 conditions give beta_31, beta_32 from bhat_3, and the
+# two remaining conditions fix beta_21 and leave b_4 free.  Free parameters:
+# alpha_2 = 0.6, alpha_3 = 0.7, bhat_3 = 0.4, b_4 = 0.6 (chosen for small
+# coefficients and an embedded method stable on the imaginary axis).
+# ---------------------------------------------------------------------------
+ROS4_FREE = dict(a2=0.6, a3=0.7, bh3=0.4, b4=0.6)
+
+
+def ros4_gamma():
+    from math import comb, factorial
+    coef = [comb(4, j) * (-1) ** j / factorial(4 - j) for j in range(5)]  # powers of gamma
+    roots = np.roots(coef[::-1])
+    return max(r.real for r in roots if abs(r.imag) < 1e-12 and 0.2 < r.real < 0.6)
+
+
+def ros4(a2=ROS4_FREE["a2"], a3=ROS4_FREE["a3"], bh3=ROS4_FREE["bh3"], b4=ROS4_FREE["b4"]):
+    """Order-4 tableau (float64) in both forms."""
+    G = ros4_gamma()
+    K2, K3, K6 = 0.5 - G, 1 / 6 - G + G * G, 1 / 8 - G / 3
+    K7, K8 = 1 / 12 - G / 3, 1 / 24 - G / 2 + 1.5 * G * G - G**3
+    b2, s = np.linalg.solve([[a2**2, a3**2], [a2**3, a3**3]], [1 / 3, 1 / 4])
+    b1, b3 = 1 - b2 - s, s - b4
+    be21 = a2**2 * (K3 - K8 * K2 / K3) / (K7 - K8 / (3 * K3))
+    a32 = K6 / (a3 * be21 * s)
+    a31 = a3 - a32
+    bh2 = (1 / 3 - bh3 * a3**2) / a2**2
+    bh1 = 1 - bh2 - bh3
+    be32 = K3 / (bh3 * be21)
+    B3 = (K2 - bh2 * be21) / bh3
+    be31 = B3 - be32
+    be43 = K8 / (b4 * be32 * be21)
+    be42 = (K3 - b3 * be32 * be21 - b4 * be43 * B3) / (b4 * be21)
+    B4 = (K2 - b2 * be21 - b3 * B3) / b4
+    be41 = B4 - be42 - be43
+    alpha = np.array([[0, 0, 0, 0], [a2, 0, 0, 0], [a31, a32, 0, 0], [a31, a32, 0, 0]], float)
+    beta = np.array([[G, 0, 0, 0], [be21, G, 0, 0], [be31, be32, G, 0], [be41, be42, be43, G]], float)
+    b = np.array([b1, b2, b3, b4])
+    bh = np.array([bh1, bh2, bh3, 0.0])
+    Gam = beta - alpha
+    Gi = np.linalg.inv(Gam)
+    clean = lambda M: np.where(np.abs(M) < 1e-13, 0.0, np.tril(M, -1))  # exact zeros stay zero
+    a = clean(alpha @ Gi)
+    c = clean(np.diag(1 / np.diag(Gam)) - Gi)
+    return dict(gamma=G, alpha=alpha, beta=beta, b=b, bhat=bh, a=a, c=c, m=b @ Gi, mhat=bh @ Gi,
+                stages=4, order=4, embedded_order=3, reuse=[0, -1, -1, 2])
+
+
+def ros4_residuals(t=None):
+    """Order-4 conditions for b and order-3 conditions for bhat (all ~0) and
+    the order-4 conditions for bhat (not all 0)."""
+    t = t or ros4()
+    G, al, be = t["gamma"], t["alpha"], t["beta"]
+    bp = np.array([be[i, :i].sum() for i in range(4)])
+    ai = al.sum(1)
+
+    def conds(b):
+        return np.array([
+            b.sum() - 1, b @ bp - (0.5 - G), b @ ai**2 - 1 / 3,
+            sum(b[i] * be[i, j] * bp[j] for i in range(4) for j in range(i)) - (1 / 6 - G + G * G),
+            b @ ai**3 - 0.25,
+            sum(b[i] * ai[i] * al[i, j] * bp[j] for i in range(4) for j in range(i)) - (1 / 8 - G / 3),
+            sum(b[i] * be[i, j] * ai[j] ** 2 for i in range(4) for j in range(i)) - (1 / 12 - G / 3),
+            sum(b[i] * be[i, j] * be[j, k] * bp[k] for i in range(4) for j in range(i) for k in range(j))
+            - (1 / 24 - G / 2 + 1.5 * G * G - G**3)])
+    return conds(t["b"]), conds(t["bhat"])
+
+
 def stability(z, t=None, embedded=False):
     """R(z) = 1 + z b^T (I - z B)^-1 1 with B = (beta_ij) (diagonal gamma)."""
-    t = t or tableau()
+    t = t or ros4()
     B = np.array([[float(x) for x in r] for r in t["beta"]])
     b = np.array([float(x) for x in (t["bhat"] if embedded else t["b"])])
     z = np.atleast_1d(np.asarray(z, dtype=complex))
@@ -138,23 +220,23 @@ def check():
     return dict(conds=conds, R_inf=rinf, max_R_imag_axis=rmax)
 
 
-def c_constants():
-    """C initialisers of the transformed tableau for the device code."""
-    t = tableau()
+def c_constants(t=None):
+    """Device initialisers of the transformed tableau (17 significant digits)."""
+    t = t or ros4()
     f = lambda x: repr(float(x))
-    s = t["stages"]
-    lines = [f"// gamma = {t['gamma']}"]
-    lines.append("ROS_GAMMA = " + f(t["gamma"]))
-    for i in range(s):
-        lines.append(f"a[{i}] = {{" + ", ".join(f(t['a'][i][j]) for j in range(s)) + "}")
-    for i in range(s):
-        lines.append(f"c[{i}] = {{" + ", ".join(f(t['c'][i][j]) for j in range(s)) + "}")
-    lines.append("m = {" + ", ".join(f(x) for x in t["m"]) + "}")
-    lines.append("e = {" + ", ".join(f(x - y) for x, y in zip(t["m"], t["mhat"])) + "}")
-    return "\n".join(lines)
+    rows = lambda M: "{" + ", ".join("{" + ", ".join(f(x) for x in r) + "}" for r in M) + "}"
+    return "\n".join([
+        f"GAM = {f(t['gamma'])}",
+        f"TA = {rows(t['a'])}",
+        f"TC = {rows(t['c'])}",
+        "TM = {" + ", ".join(f(x) for x in t["m"]) + "}",
+        "TE = {" + ", ".join(f(x - y) for x, y in zip(t["m"], t["mhat"])) + "}",
+        "TREUSE = {" + ", ".join(str(x) for x in t["reuse"]) + "}",
+    ])
 
 
 if __name__ == "__main__":
     print(derive())
     print(check())
+    print(ros4_residuals())
     print(c_constants())

@@ -63,10 +63,10 @@ def parity_excess(T, Y, Tref, Yref):
     return np.maximum(eT, eY.max(1))
 
 
-def gross_scale(o, mech, T, p, Y):
+def gross_scale(o, mech, T, p, Y, dlnA=None):
     """Per component, sum_j |nu_ij| (|forward| + |reverse| rate) mapped to dY/dt
     and dT/dt units: the size of the terms whose roundoff the RHS carries."""
-    kf, kr, q, wdot, aux = o.rates(T, p, Y)
+    kf, kr, q, wdot, aux = o.rates(T, p, Y, dlnA)
     rho, cp = aux[0], aux[1]
     W = mech.molar_masses()
     C = rho * Y / W
@@ -94,14 +94,17 @@ def test_rhs_parity(torch, sc, oracle_mod, key, ncell):
     idx = np.sort(rng.choice(c["T"].size, ncell, replace=False))
     plan = sc.Plan(sc.Mechanism(mech.to_text()))
     T, p, Y, _ = to_gpu(torch, c, idx)
-    fT, fY = plan.rhs(T, p, Y)
+    # per-reaction log multipliers, indexed as in the mechanism text (the
+    # kernels run reactions in their own order)
+    dlnA = rng.normal(size=mech.n_reactions) * 0.3
+    fT, fY = plan.rhs(T, p, Y, dlnA=dlnA)
     fT, fY = fT.cpu().numpy(), fY.cpu().numpy().T
     o = oracle_mod.Oracle(mech.to_text())
     worst = 0.0
     for n, i in enumerate(idx):
         y = np.append(c["Y"][i], c["T"][i])
-        f = o.rhs(y, c["p"][i])
-        sY, sT = gross_scale(o, mech, c["T"][i], c["p"][i], c["Y"][i])
+        f = o.rhs(y, c["p"][i], dlnA=dlnA)
+        sY, sT = gross_scale(o, mech, c["T"][i], c["p"][i], c["Y"][i], dlnA)
         eY = np.abs(fY[n] - f[:-1]) / (sY + 1e-300)
         eT = abs(fT[n] - f[-1]) / (sT + 1e-300)
         worst = max(worst, eY.max(), eT)
@@ -117,12 +120,13 @@ def test_jacobian_parity(torch, sc, oracle_mod, key, ncell):
     idx = np.sort(rng.choice(c["T"].size, ncell, replace=False))
     plan = sc.Plan(sc.Mechanism(mech.to_text()))
     T, p, Y, _ = to_gpu(torch, c, idx)
-    J = plan.jacobian(T, p, Y).cpu().numpy()
+    dlnA = rng.normal(size=mech.n_reactions) * 0.3
+    J = plan.jacobian(T, p, Y, dlnA=dlnA).cpu().numpy()
     o = oracle_mod.Oracle(mech.to_text())
     worst = 0.0
     for n, i in enumerate(idx):
         y = np.append(c["Y"][i], c["T"][i])
-        Jc = o.jac_cs(y, c["p"][i])
+        Jc = o.jac_cs(y, c["p"][i], dlnA=dlnA)
         row = np.abs(Jc).max(1, keepdims=True) + 1e-300
         err = np.abs(J[n] - Jc) / (1e-8 * np.abs(Jc) + 1e-12 * row)
         worst = max(worst, err.max())

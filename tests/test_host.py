@@ -128,19 +128,57 @@ def test_tableau_convergence_order():
         assert all(abs(o - order) < 0.15 for o in obs), (order, obs)
 
 
+def test_order4_tableau_conditions_and_order():
+    """The device method: order-4 conditions hold, the embedded method has
+    order 3 (not 4), L-stability, and observed orders 4 and 3."""
+    from scipy.integrate import solve_ivp
+    r4, r3 = tableau.ros4_residuals()
+    assert np.abs(r4).max() < 1e-14
+    assert np.abs(r3[:4]).max() < 1e-14 and np.abs(r3[4:]).max() > 1e-3
+    t = tableau.ros4()
+    assert abs(tableau.stability(1e12, t)[0]) < 1e-9
+    assert np.abs(tableau.stability(1j * np.logspace(-3, 4, 300), t)).max() <= 1 + 1e-12
+    # stage 4 is evaluated where stage 3 is
+    assert np.array_equal(t["alpha"][3], t["alpha"][2]) and np.array_equal(t["a"][3], t["a"][2])
+    f = lambda y: np.array([y[1], -y[0] - 0.5 * y[0] ** 3])
+    J = lambda y: np.array([[0.0, 1.0], [-1.0 - 1.5 * y[0] ** 2, 0.0]])
+
+    def run(w, n):
+        y = np.array([1.0, 0.0])
+        h = 2.0 / n
+        for _ in range(n):
+            M = np.eye(2) / (h * t["gamma"]) - J(y)
+            U = []
+            for i in range(4):
+                Yi = y + sum(t["a"][i, j] * U[j] for j in range(i))
+                U.append(np.linalg.solve(M, f(Yi) + sum(t["c"][i, j] / h * U[j] for j in range(i))))
+            y = y + sum(w[i] * U[i] for i in range(4))
+        return y
+
+    ref = solve_ivp(lambda _, y: f(y), (0, 2.0), [1.0, 0.0], method="DOP853", rtol=1e-13, atol=1e-14).y[:, -1]
+    for w, order in ((t["m"], 4), (t["mhat"], 3)):
+        e = [np.abs(run(w, n) - ref).max() for n in (20, 40, 80)]
+        obs = np.log2(e[0] / e[1]), np.log2(e[1] / e[2])
+        assert all(abs(o - order) < 0.15 for o in obs), (order, obs)
+
+
 def test_device_tableau_matches_derivation():
-    """The constants compiled into the kernels equal the derived tableau."""
+    """The constants compiled into the kernels equal the derived order-4 tableau."""
     src = open(os.path.join(ROOT, "paper_2311_14941_amd", "csrc", "kernels.hip")).read()
-    t = tableau.tableau()
-    num = lambda s: [eval(x) for x in re.findall(r"-?[0-9.]+(?:\s*/\s*[0-9.]+)?", s)]
+    t = tableau.ros4()
+    num = lambda s: [float(x) for x in re.findall(r"-?[0-9]+\.[0-9]+(?:e-?[0-9]+)?", s)]
     TA = num(re.search(r"TA\[NS\]\[NS\] = \{(.*?)\};", src, re.S).group(1))
     TC = num(re.search(r"TC\[NS\]\[NS\] = \{(.*?)\};", src, re.S).group(1))
     TM = num(re.search(r"TM\[NS\] = \{(.*?)\};", src, re.S).group(1))
     TE = num(re.search(r"TE\[NS\] = \{(.*?)\};", src, re.S).group(1))
-    assert np.allclose(TA, np.array(t["a"], float).ravel())
-    assert np.allclose(TC, np.array(t["c"], float).ravel())
-    assert np.allclose(TM, [float(x) for x in t["m"]])
-    assert np.allclose(TE, [float(x - y) for x, y in zip(t["m"], t["mhat"])])
+    GAM = float(re.search(r"constexpr double GAM = ([0-9.e-]+);", src).group(1))
+    assert GAM == t["gamma"]
+    assert np.array_equal(TA, t["a"].ravel())
+    assert np.array_equal(TC, t["c"].ravel())
+    assert np.array_equal(TM, t["m"])
+    assert np.array_equal(TE, t["m"] - t["mhat"])
+    reuse = [int(x) for x in re.search(r"TREUSE\[NS\] = \{(.*?)\};", src).group(1).split(",")]
+    assert reuse == t["reuse"]
 
 
 # ------------------------------------------------------------------ generator
