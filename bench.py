@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--cells", type=int, default=65536)
     ap.add_argument("--mode", default="plain", choices=["plain", "persistent"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
+                    help="c2: the headline (default); c3: the uneven batch, queue vs static mapping")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the batch of independent "
@@ -78,6 +80,8 @@ def main():
     from synth.cells import make_cells
 
     sc.ensure_built()
+    if args.workload == "c3":
+        return bench_uneven(args)
     log("bench: generating C2 workload")
     cells = make_cells("C2")
     n = args.cells
@@ -138,6 +142,63 @@ def main():
         log("bench: CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(cells)
     print(json.dumps(res), flush=True)
+
+
+def bench_uneven(args):
+    """Uneven batch: 262,144 cells of the C2 classes with per-cell dt
+    log-uniform in [1e-7, 1e-3] s (step counts spread > 100x), 53-species
+    mechanism.  Static cell-to-workgroup mapping (baseline) against the
+    persistent queue in the configuration the autotuner picks."""
+    import torch
+    import paper_2311_14941_amd as sc
+    from paper_2311_14941_amd import autotune
+    from synth.cells import make_cells
+    log("bench: generating the uneven batch")
+    cells = make_cells("C3s")
+    n = cells["T"].size
+    dev = "cuda:0"
+    T = torch.tensor(cells["T"], device=dev)
+    p = torch.tensor(cells["p"], device=dev)
+    Y = torch.tensor(np.ascontiguousarray(cells["Y"].T), device=dev)
+    dt = torch.tensor(cells["dt"], device=dev)
+    mech = sc.Mechanism(cells["mech"].to_text())
+    log("bench: autotuning on a 16,384-cell sample")
+    s = np.random.default_rng(0).choice(n, 16384, replace=False)
+    ts = torch.tensor(s, device=dev)
+    best, times = autotune.tune(mech, T[ts].contiguous(), p[ts].contiguous(), Y[:, ts].contiguous(),
+                                dt[ts].contiguous(), use_cache=False, reps=1, verbose=True)
+
+    def timed(plan, prev=None):
+        out = plan.integrate(T, p, Y, dt) if prev is None else prev
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(args.steps):
+            a.record()
+            out = plan.integrate(T, p, Y, dt, out=out)
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms)), out
+
+    res = {}
+    for name, cfg in (("static", dict(mode="static")), ("plain", dict(mode="plain")),
+                      ("persistent_tuned", best)):
+        log(f"bench: {name}")
+        ms, out = timed(sc.Plan(mech, **cfg))
+        res[name] = ms
+    steps = (out["n_acc"] + out["n_rej"]).cpu().numpy()
+    line = {"metric": "uneven batch: cells/s, persistent queue vs static mapping", "unit": "cells/s",
+            "value": n / (res["persistent_tuned"] / 1e3), "n_gpus": 1, "steps": args.steps,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "262,144 cells, 53-species mechanism, C2 classes, dt log-uniform 1e-7..1e-3 s, "
+                                   "rtol 1e-6", "tuned": best},
+            "ms": res, "speedup_vs_static": res["static"] / res["persistent_tuned"],
+            "speedup_vs_plain": res["plain"] / res["persistent_tuned"],
+            "steps_per_cell": {"mean": float(steps.mean()), "p50": float(np.median(steps)),
+                               "max": int(steps.max()), "spread_max_over_p10": float(steps.max() / max(1, np.percentile(steps, 10)))},
+            "tuning_sample_ms": times}
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -52,8 +52,18 @@ enum {
 
 /* integration modes */
 enum {
-    SC_MODE_PLAIN = 0,     /* one workgroup per cell, grid = cells */
-    SC_MODE_PERSISTENT = 1 /* resident grid pulling cell tiles from a queue */
+    SC_MODE_PLAIN = 0,      /* one workgroup per cell, grid = cells */
+    SC_MODE_PERSISTENT = 1, /* resident grid pulling cell tiles from a queue */
+    SC_MODE_STATIC = 2      /* resident grid, workgroup w owns a fixed contiguous
+                               group of cells (the static-mapping baseline) */
+};
+
+/* persistent-mode cell order */
+enum {
+    SC_ORDER_NONE = 0,     /* cells in index order */
+    SC_ORDER_DT = 1,       /* longest dt first */
+    SC_ORDER_COST = 2      /* most steps first, by the incoming n_acc + n_rej
+                              (the previous call's counts: measured cost) */
 };
 
 typedef struct sc_mech sc_mech; /* immutable after load; shareable across threads */
@@ -65,8 +75,9 @@ typedef struct {
     int32_t max_steps;  /* accepted + rejected steps per cell (default 100000) */
     int32_t mode;       /* SC_MODE_PLAIN or SC_MODE_PERSISTENT */
     int32_t tile;       /* persistent mode: cells per queue pull (default 1) */
-    int32_t grid;       /* persistent mode: workgroups; 0 = resident capacity */
-    int32_t order;      /* persistent mode: 1 = pull cells longest-dt first */
+    int32_t grid;       /* persistent/static modes: workgroups; 0 = resident capacity */
+    int32_t order;      /* persistent mode: SC_ORDER_* (sorting needs a workspace
+                           that sc_integrate allocates on first use) */
     int32_t reserved;
 } sc_options;
 
@@ -122,6 +133,8 @@ sc_status sc_linsolve(sc_plan *plan, int64_t n, const double *T, const double *p
                       void *hip_stream);
 
 /* Integrate n cells over their own dt[c] at constant p[c].
+ * With SC_ORDER_COST, n_acc and n_rej are read (as the predicted cost of each
+ * cell) before they are overwritten; they must then be non-NULL. 
  *   in : T0[n], p[n], Y0[N*ld], dt[n], dlnA[R] or NULL,
  *        h_io[n] or NULL (initial step; the last accepted step is written back)
  *   out: T1[n], Y1[N*ld] (may alias T0/Y0), cell_status[n],

@@ -22,7 +22,8 @@ LIBPATH = os.path.join(HERE, "libstiffchem.so")
 
 SC_OK, SC_EINVAL, SC_EPARSE, SC_ENOMEM, SC_EHIP, SC_EUNSUPPORTED, SC_EBUDGET = 0, -1, -2, -3, -4, -5, -6
 CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_BAD_INPUT = range(5)
-MODES = {"plain": 0, "persistent": 1}
+MODES = {"plain": 0, "persistent": 1, "static": 2}
+ORDERS = {"none": 0, "dt": 1, "cost": 2}
 
 
 class StiffchemError(RuntimeError):
@@ -131,7 +132,7 @@ class Plan:
     """A mechanism on one device with integration options."""
 
     def __init__(self, mech: Mechanism, device: int = 0, rtol=1e-6, atol=1e-12, max_steps=100000,
-                 mode="plain", tile=1, grid=0):
+                 mode="plain", tile=1, grid=0, order="none"):
         import torch
         self.torch = torch
         self.mech = mech
@@ -139,7 +140,8 @@ class Plan:
         opt = Options()
         lib().sc_default_options(C.byref(opt))
         opt.rtol, opt.atol, opt.max_steps = rtol, atol, max_steps
-        opt.mode, opt.tile, opt.grid = MODES[mode], tile, grid
+        opt.mode, opt.tile, opt.grid, opt.order = MODES[mode], tile, grid, ORDERS[order]
+        self.config = dict(mode=mode, tile=tile, grid=grid, order=order)
         self.options = opt
         h = _P()
         _check(lib().sc_plan_create(mech._h, device, C.byref(opt), C.byref(h)))
@@ -227,6 +229,63 @@ class Plan:
         if hio is not None:
             out["h"] = hio
         return out
+
+
+class Chain:
+    """Successive integrations of the same cells (operator-split substeps:
+    the state and the step size carry from one substep to the next), captured
+    once into a HIP graph and replayed.  Buffers are allocated up front so the
+    captured launches read and write fixed addresses."""
+
+    def __init__(self, plan: "Plan", T0, p, Y0, dt, nsub: int, dlnA=None, graph=True):
+        t = plan.torch
+        self.plan, self.nsub = plan, nsub
+        T0, p, Y0, n = plan._state(T0, p, Y0)
+        dt = plan._dev(dt)
+        if dt.dim() == 0:
+            dt = dt.expand(n).contiguous()
+        self.n = n
+        self.T = [T0.clone() for _ in range(2)]
+        self.Y = [Y0.clone() for _ in range(2)]
+        self.p, self.dt = p, dt
+        self.d = plan._dlnA(dlnA)
+        self.h = t.zeros(n, dtype=t.float64, device=T0.device)
+        mk = lambda: t.zeros(n, dtype=t.int32, device=T0.device)
+        self.status, self.n_acc, self.n_rej = mk(), mk(), mk()
+        self.steps = mk()
+        self.graph = None
+        if graph:
+            s = t.cuda.Stream(device=T0.device)
+            s.wait_stream(t.cuda.current_stream(T0.device))
+            with t.cuda.stream(s):  # warm-up outside capture (lazy setup)
+                self._launch_all()
+            t.cuda.current_stream(T0.device).wait_stream(s)
+            self.graph = t.cuda.CUDAGraph()
+            with t.cuda.graph(self.graph):
+                self._launch_all()
+
+    def _launch_all(self):
+        plan, L = self.plan, lib()
+        for k in range(self.nsub):
+            a, b = k % 2, (k + 1) % 2
+            _check(L.sc_integrate(plan._h, self.n, _ptr(self.T[a]), _ptr(self.p), _ptr(self.Y[a]), self.n,
+                                  _ptr(self.dt), _ptr(self.d), _ptr(self.h), _ptr(self.T[b]), _ptr(self.Y[b]),
+                                  _ptr(self.status), _ptr(self.n_acc), _ptr(self.n_rej),
+                                  _stream(plan.torch, plan.device)))
+            self.steps.add_(self.n_acc).add_(self.n_rej)
+
+    def run(self, T0, Y0, h0=None):
+        """Load the initial state, run all substeps; returns (T, Y, h, steps)."""
+        self.T[0].copy_(self.plan._dev(T0))
+        self.Y[0].copy_(self.plan._dev(Y0))
+        self.h.zero_() if h0 is None else self.h.copy_(self.plan._dev(h0))
+        self.steps.zero_()
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self._launch_all()
+        last = self.nsub % 2
+        return self.T[last], self.Y[last], self.h, self.steps
 
 
 def ensure_built():

@@ -27,6 +27,8 @@ struct sc_plan {
     std::vector<void *> allocs;
     unsigned long long *queue = nullptr;
     int capacity = 0;
+    void *order_ws = nullptr;  // cell-ordering workspace (grown on demand)
+    size_t order_ws_bytes = 0;
 };
 
 namespace {
@@ -64,6 +66,9 @@ void release(sc_plan *p)
     (void)hipSetDevice(p->device);
     for (void *d : p->allocs) (void)hipFree(d);
     p->allocs.clear();
+    if (p->order_ws) (void)hipFree(p->order_ws);
+    p->order_ws = nullptr;
+    p->order_ws_bytes = 0;
     (void)hipSetDevice(cur);
 }
 
@@ -181,7 +186,9 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
     if (!(o.rtol > 0) || !(o.atol > 0) || !std::isfinite(o.rtol) || !std::isfinite(o.atol))
         return fail(SC_EINVAL, "rtol and atol must be positive and finite");
     if (o.max_steps <= 0) return fail(SC_EINVAL, "max_steps must be positive");
-    if (o.mode != SC_MODE_PLAIN && o.mode != SC_MODE_PERSISTENT) return fail(SC_EINVAL, "unknown mode");
+    if (o.mode != SC_MODE_PLAIN && o.mode != SC_MODE_PERSISTENT && o.mode != SC_MODE_STATIC)
+        return fail(SC_EINVAL, "unknown mode");
+    if (o.order < SC_ORDER_NONE || o.order > SC_ORDER_COST) return fail(SC_EINVAL, "unknown cell order");
     if (o.tile <= 0) o.tile = 1;
     if (o.grid < 0) return fail(SC_EINVAL, "grid must be >= 0");
     DeviceGuard g(device);
@@ -324,11 +331,25 @@ sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double 
         int grid = plan->opt.grid > 0 ? plan->opt.grid : plan->capacity;
         if (grid <= 0) grid = 1;
         if (grid > tiles) grid = (int)tiles;
+        int32_t *perm = nullptr;
+        if (plan->opt.order == SC_ORDER_COST && (!n_acc || !n_rej))
+            return fail(SC_EINVAL, "cost ordering needs the previous n_acc and n_rej");
+        if (plan->opt.order != SC_ORDER_NONE) {
+            e = scdev::order_cells(plan->opt.order, n, dt, n_acc, n_rej, &plan->order_ws, &plan->order_ws_bytes, &perm,
+                                   st);
+            if (e != hipSuccess) return hip_fail(e, "cell ordering");
+        }
         e = scdev::launch_zero_u64(plan->queue, st);
         if (e == hipSuccess)
             e = scdev::launch_integrate_persistent(plan->np, plan->dm, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1,
-                                                   Y1, cell_status, n_acc, n_rej, plan->queue, nullptr, tile,
+                                                   Y1, cell_status, n_acc, n_rej, plan->queue, perm, tile,
                                                    grid, st);
+    } else if (plan->opt.mode == SC_MODE_STATIC) {
+        int grid = plan->opt.grid > 0 ? plan->opt.grid : plan->capacity;
+        if (grid <= 0) grid = 1;
+        if (grid > n) grid = (int)n;
+        e = scdev::launch_integrate_static(plan->np, plan->dm, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1,
+                                           cell_status, n_acc, n_rej, grid, st);
     } else {
         e = scdev::launch_integrate(plan->np, plan->dm, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, cell_status,
                                     n_acc, n_rej, st);

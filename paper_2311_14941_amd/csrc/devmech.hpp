@@ -66,6 +66,12 @@ hipError_t launch_integrate_persistent(int np, const DevMech &m, const Opts &o, 
                                        const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st,
                                        int32_t *na, int32_t *nr, unsigned long long *queue,
                                        const int32_t *perm, int tile, int grid, hipStream_t s);
+hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0,
+                                   const double *p, const double *Y0, int64_t ld, const double *dt,
+                                   const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st,
+                                   int32_t *na, int32_t *nr, int grid, hipStream_t s);
+hipError_t order_cells(int order, int64_t n, const double *dt, const int32_t *na, const int32_t *nr,
+                       void **ws, size_t *ws_bytes, int32_t **perm, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
 int persistent_capacity(int np, int device);
 size_t lds_bytes_for(int np);

@@ -19,6 +19,8 @@
 #include <cmath>
 #include <cstdint>
 
+#include <hipcub/hipcub.hpp>
+
 #include "devmech.hpp"
 
 namespace scdev {
@@ -361,10 +363,12 @@ struct RowCoef {
     double alpha, beta, alphaT, betaT;
 };
 
-// Jacobian pass: f(y) plus the analytical terms, finalised in LDS.
+// Jacobian pass: f(y) plus the analytical terms, finalised in LDS.  With
+// Q != nullptr the rates of progress q_j are kept there (execution order),
+// for the parameter part of vector-Jacobian products.
 template <int NP>
 __device__ double rhs_jac(const DevMech &m, double *lds, double y, double p, const double *dlnA, int lane,
-                          RowCoef &rc)
+                          RowCoef &rc, double *Q = nullptr, Mix *xout = nullptr)
 {
     const int N = m.N, R = m.R;
     double *P = lds + Lds<NP>::P;
@@ -381,6 +385,7 @@ __device__ double rhs_jac(const DevMech &m, double *lds, double y, double p, con
         const double dl = dlnA ? dlnA[m.rx[j].orig] : 0.0;
         const RxOut o = reaction<true>(m, lds, j, x, dl, Lds<NP>::C, Lds<NP>::G, Lds<NP>::H);
         scatter<NP, true>(m, lds, j, o, o.dH * RT);
+        if (Q) Q[j] = o.q;
     }
     wave_sync();
     double f = 0.0, hw = 0.0, eu = 0.0, cpf = 0.0, dcp = 0.0, uk = 0.0, Wk = 0.0;
@@ -417,6 +422,7 @@ __device__ double rhs_jac(const DevMech &m, double *lds, double y, double p, con
     } else {
         rc = RowCoef{0.0, 0.0, 0.0, 0.0};
     }
+    if (xout) *xout = x;
     return f;
 }
 
@@ -511,19 +517,71 @@ __device__ __forceinline__ double lu_solve(const double *F, double dinv, double 
     return lane < NP ? b : 0.0;
 }
 
-// Form, factorise and park M = I/hg - J; returns 1/U_ii of this lane.
+// Form, factorise and park M = I/hg - J in F (the LDS term region itself,
+// or per-cell global scratch); returns 1/U_ii of this lane.
 template <int NP>
 __device__ __forceinline__ double factor_matrix(const DevMech &m, double *lds, const RowCoef &rc, int lane,
-                                                double inv_hg)
+                                                double inv_hg, double *F)
 {
     double dinv;
     double a[NP];
     form_matrix<NP>(m, lds, rc, lane, inv_hg, a);
     lu_factor<NP>(a, dinv, lane);
     wave_sync();  // every lane has read its row of the terms
-    store_factors<NP>(lds + Lds<NP>::P, a, lane);
+    store_factors<NP>(F, a, lane);
     wave_sync();
     return dinv;
+}
+
+// One Rosenbrock attempt of size hc from y: Jacobian pass, factorisation
+// (parked in F), the four stages (stage vectors u_i left in LDS) and the
+// embedded error.  Returns the new state; *err gets the scaled RMS error.
+// Forward integration and adjoint replay both call this, so a replayed
+// step reproduces the recorded one bit for bit.
+template <int NP>
+__device__ double ros_attempt(const DevMech &m, const Opts &o, double *lds, double *F, double y, double p,
+                              const double *dlnA, int lane, double hc, double *err)
+{
+    const int n = m.N + 1;
+    double *U = lds + Lds<NP>::U;
+    RowCoef rc;
+    const double f0 = rhs_jac<NP>(m, lds, y, p, dlnA, lane, rc);
+    const double dinv = factor_matrix<NP>(m, lds, rc, lane, 1.0 / (GAM * hc), F);
+    const double ih = 1.0 / hc;
+    double flast = f0;
+#pragma unroll 1
+    for (int i = 0; i < NS; ++i) {
+        double fi;
+        const int reuse = TREUSE[i];
+        if (reuse == 0) {
+            fi = f0;
+        } else if (reuse > 0) {
+            fi = flast;  // the stage it names is the last one evaluated
+        } else {
+            double ys = y;
+            for (int j = 0; j < i; ++j) ys += TA[i][j] * U[j * WAVE + lane];
+            fi = rhs<NP>(m, lds, ys, p, dlnA, lane);
+            flast = fi;
+        }
+        for (int j = 0; j < i; ++j) fi += (TC[i][j] * ih) * U[j * WAVE + lane];
+        if (lane >= n) fi = 0.0;
+        U[i * WAVE + lane] = lu_solve<NP>(F, dinv, fi, lane);
+    }
+    double ynew = y, ev = 0.0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const double ui = U[i * WAVE + lane];
+        ynew += TM[i] * ui;
+        ev += TE[i] * ui;
+    }
+    double e2 = 0.0;
+    if (lane < n) {
+        const double sc = o.atol + o.rtol * fmax(fabs(y), fabs(ynew));
+        const double r = ev / sc;
+        e2 = r * r;
+    }
+    *err = sqrt(wave_sum(e2) / n);
+    return ynew;
 }
 
 // ---------------------------------------------------------------------------
@@ -586,7 +644,7 @@ __global__ void __launch_bounds__(WAVE) k_linsolve(DevMech m, int64_t n, const d
     const double y = load_state(m, T, Y, ld, c, lane);
     RowCoef rc;
     rhs_jac<NP>(m, lds, y, p[c], dlnA, lane, rc);
-    const double dinv = factor_matrix<NP>(m, lds, rc, lane, 1.0 / hg[c]);
+    const double dinv = factor_matrix<NP>(m, lds, rc, lane, 1.0 / hg[c], lds + Lds<NP>::P);
     const int nn = m.N + 1;
     const double bb = lane < nn ? b[c * nn + lane] : 0.0;
     const double xx = lu_solve<NP>(lds + Lds<NP>::P, dinv, bb, lane);
@@ -610,7 +668,6 @@ __device__ void integrate_cell(const DevMech &m, const Opts &o, double *lds, int
                      !(dt >= 0.0) || !isfinite(dt);
     int st = SC_CELL_OK, nacc = 0, nrej = 0;
     double hnext = dt;
-    double *U = lds + Lds<NP>::U;
     if (bad) {
         st = SC_CELL_BAD_INPUT;
     } else if (dt > 0.0) {
@@ -628,46 +685,11 @@ __device__ void integrate_cell(const DevMech &m, const Opts &o, double *lds, int
             if (h < 1e-20 * dt) { st = SC_CELL_H_UNDERFLOW; break; }
             // Jacobian terms at y (recomputed after a rejection too: their LDS
             // region holds the LU factors while the stages run)
-            RowCoef rc;
-            const double f0 = rhs_jac<NP>(m, lds, y, p, dlnA, lane, rc);
             bool last = false;
             double hc = h;
             if (t + hc >= dt) { hc = dt - t; last = true; }
-            const double dinv = factor_matrix<NP>(m, lds, rc, lane, 1.0 / (GAM * hc));
-            const double ih = 1.0 / hc;
-            double flast = f0;
-#pragma unroll 1
-            for (int i = 0; i < NS; ++i) {
-                double fi;
-                const int reuse = TREUSE[i];
-                if (reuse == 0) {
-                    fi = f0;
-                } else if (reuse > 0) {
-                    fi = flast;  // the stage it names is the last one evaluated
-                } else {
-                    double ys = y;
-                    for (int j = 0; j < i; ++j) ys += TA[i][j] * U[j * WAVE + lane];
-                    fi = rhs<NP>(m, lds, ys, p, dlnA, lane);
-                    flast = fi;
-                }
-                for (int j = 0; j < i; ++j) fi += (TC[i][j] * ih) * U[j * WAVE + lane];
-                if (lane >= n) fi = 0.0;
-                U[i * WAVE + lane] = lu_solve<NP>(lds + Lds<NP>::P, dinv, fi, lane);
-            }
-            double ynew = y, ev = 0.0;
-#pragma unroll
-            for (int i = 0; i < NS; ++i) {
-                const double ui = U[i * WAVE + lane];
-                ynew += TM[i] * ui;
-                ev += TE[i] * ui;
-            }
-            double e2 = 0.0;
-            if (lane < n) {
-                const double sc = o.atol + o.rtol * fmax(fabs(y), fabs(ynew));
-                const double r = ev / sc;
-                e2 = r * r;
-            }
-            const double err = sqrt(wave_sum(e2) / n);
+            double err;
+            const double ynew = ros_attempt<NP>(m, o, lds, lds + Lds<NP>::P, y, p, dlnA, lane, hc, &err);
             if (!isfinite(err)) {
                 ++nrej;
                 h = hc * 0.2;
@@ -746,7 +768,36 @@ __global__ void __launch_bounds__(WAVE) k_integrate_persistent(DevMech m, Opts o
     }
 }
 
+// Static mapping (the baseline the queue is compared with): workgroup w owns
+// cells [w*group, (w+1)*group) and integrates them one after another.
+template <int NP>
+__global__ void __launch_bounds__(WAVE) k_integrate_static(DevMech m, Opts o, int64_t n, const double *T0,
+                                                           const double *P, const double *Y0, int64_t ld,
+                                                           const double *DT, const double *dlnA, double *h_io,
+                                                           double *T1, double *Y1, int32_t *status, int32_t *nacc,
+                                                           int32_t *nrej, int64_t group)
+{
+    extern __shared__ double lds[];
+    const int64_t c0 = (int64_t)blockIdx.x * group;
+    const int64_t c1 = min(c0 + group, n);
+#pragma unroll 1
+    for (int64_t c = c0; c < c1; ++c)
+        integrate_cell<NP>(m, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
+}
+
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+
+__global__ void k_iota(int32_t *v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (int32_t)i;
+}
+
+__global__ void k_cost(const int32_t *na, const int32_t *nr, int32_t *key, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) key[i] = na[i] + nr[i];
+}
 
 // ---------------------------------------------------------------------------
 // launchers (host)
@@ -807,6 +858,62 @@ hipError_t launch_integrate_persistent(int np, const DevMech &m, const Opts &o, 
                                        lds_bytes<NPV>(), s, m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na,
                                        nr, queue, perm, tile));
     return hipGetLastError();
+}
+
+hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0,
+                                   const double *p, const double *Y0, int64_t ld, const double *dt,
+                                   const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st,
+                                   int32_t *na, int32_t *nr, int grid, hipStream_t s)
+{
+    const int64_t group = (n + grid - 1) / grid;
+    const unsigned g = (unsigned)((n + group - 1) / group);
+    SC_DISPATCH(np, hipLaunchKernelGGL(k_integrate_static<NPV>, dim3(g), dim3(WAVE), lds_bytes<NPV>(), s, m, o, n,
+                                       T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, group));
+    return hipGetLastError();
+}
+
+// Cell permutation for the persistent queue: indices sorted by descending
+// key (dt, or the previous call's step count), by a device radix sort.
+// `ws` is grown on demand: [perm_in | perm_out | keys_out | cost keys | temp].
+hipError_t order_cells(int order, int64_t n, const double *dt, const int32_t *na, const int32_t *nr,
+                       void **ws, size_t *ws_bytes, int32_t **perm, hipStream_t s)
+{
+    const size_t al = 256;
+    auto up = [&](size_t b) { return (b + al - 1) / al * al; };
+    size_t tmp = 0;
+    hipError_t e;
+    if (order == SC_ORDER_DT)
+        e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp, (const double *)nullptr, (double *)nullptr,
+                                                         (const int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 64,
+                                                         s);
+    else
+        e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                                         (const int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 32,
+                                                         s);
+    if (e != hipSuccess) return e;
+    const size_t b_perm = up(sizeof(int32_t) * n), b_keys = up(sizeof(double) * n);
+    const size_t need = 2 * b_perm + 2 * b_keys + up(tmp);
+    if (*ws_bytes < need) {
+        if (*ws) (void)hipFree(*ws);
+        *ws = nullptr;
+        *ws_bytes = 0;
+        if ((e = hipMalloc(ws, need)) != hipSuccess) return e;
+        *ws_bytes = need;
+    }
+    char *base = (char *)*ws;
+    int32_t *pin = (int32_t *)base, *pout = (int32_t *)(base + b_perm);
+    void *kout = base + 2 * b_perm, *kcost = base + 2 * b_perm + b_keys, *temp = base + 2 * b_perm + 2 * b_keys;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_iota, dim3(blocks), dim3(256), 0, s, pin, n);
+    if (order == SC_ORDER_DT) {
+        e = hipcub::DeviceRadixSort::SortPairsDescending(temp, tmp, dt, (double *)kout, pin, pout, (int)n, 0, 64, s);
+    } else {
+        hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(256), 0, s, na, nr, (int32_t *)kcost, n);
+        e = hipcub::DeviceRadixSort::SortPairsDescending(temp, tmp, (const int32_t *)kcost, (int32_t *)kout, pin, pout,
+                                                         (int)n, 0, 32, s);
+    }
+    *perm = pout;
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 // clears the queue counter with a kernel (safe inside captured graphs)

@@ -37,6 +37,11 @@ CONFIGS = {
     "C3": dict(mech="chon_110", n=262144, seed=203, kind="classes", dt=("loguniform", 1e-7, 1e-3)),
     "C4": dict(mech="chon_53", n=16384, seed=204, kind="classes", dt=1e-4),
     "C5": dict(mech="chon_110", n=65536, seed=205, kind="classes", dt=5e-5, substeps=20),
+    # the uneven batch of C3 (classes, per-cell LTS dt log-uniform in
+    # [1e-7, 1e-3] s) on the 53-species mechanism
+    "C3s": dict(mech="chon_53", n=262144, seed=203, kind="classes", dt=("loguniform", 1e-7, 1e-3)),
+    # the chained substeps of C5 on the 53-species mechanism
+    "C5s": dict(mech="chon_53", n=65536, seed=205, kind="classes", dt=5e-5, substeps=20),
 }
 
 FUELS = ("H2", "CH4", "NH3")

@@ -308,3 +308,56 @@ def test_h_carry(torch, sc):
     two = plan.integrate(half["T"], p, half["Y"], dt / 2, h=half["h"])
     assert torch.all(half["h"] > 0)
     assert torch.allclose(one["T"], two["T"], rtol=1e-6)
+
+
+def test_launch_modes_bitwise_equal(torch, sc):
+    """Static mapping, and the persistent queue with every cell order and tile,
+    give the plain launch's results bit for bit (per-cell arithmetic does not
+    depend on scheduling)."""
+    from synth.cells import make_cells
+    c = make_cells("C3s", n=3000)
+    mech = sc.Mechanism(c["mech"].to_text())
+    args = to_gpu(torch, c, np.arange(3000))
+    ref = sc.Plan(mech).integrate(*args)
+    for cfg in (dict(mode="static"), dict(mode="static", grid=7), dict(mode="persistent", order="dt"),
+                dict(mode="persistent", order="dt", tile=4), dict(mode="persistent", tile=3, grid=5)):
+        out = sc.Plan(mech, **cfg).integrate(*args)
+        for k in ("T", "Y", "status", "n_acc", "n_rej"):
+            assert torch.equal(ref[k], out[k]), (cfg, k)
+    # cost order reads the previous counts before overwriting them
+    plan = sc.Plan(mech, mode="persistent", order="cost")
+    out = {k: v.clone() for k, v in ref.items()}
+    out = plan.integrate(*args, out=out)
+    for k in ("T", "Y", "status", "n_acc", "n_rej"):
+        assert torch.equal(ref[k], out[k]), ("cost", k)
+
+
+def test_chained_substeps_graph_replay(torch, sc):
+    """Chained substeps captured in a HIP graph: every replay (with eager work
+    in between) equals the eager chain."""
+    c = cells("C2")
+    mech = sc.Mechanism(c["mech"].to_text())
+    idx = np.arange(0, 65536, 256)
+    T, p, Y, dt = to_gpu(torch, c, idx)
+    for mode in ("plain", "persistent"):
+        plan = sc.Plan(mech, mode=mode)
+        eager = sc.Chain(plan, T, p, Y, dt / 4, nsub=4, graph=False)
+        Te, Ye, he, se = [x.clone() for x in eager.run(T, Y)]
+        g = sc.Chain(plan, T, p, Y, dt / 4, nsub=4, graph=True)
+        for rep in range(3):
+            _ = plan.integrate(T, p, Y, dt)  # eager work between replays
+            torch.cuda.synchronize()
+            Tg, Yg, hg, sg = g.run(T, Y)
+            torch.cuda.synchronize()
+            assert torch.equal(Tg, Te) and torch.equal(Yg, Ye), (mode, rep)
+            assert torch.equal(hg, he) and torch.equal(sg, se), (mode, rep)
+
+
+def test_autotuner_picks_a_valid_config(torch, sc):
+    from paper_2311_14941_amd import autotune
+    from synth.cells import make_cells
+    c = make_cells("C3s", n=2048)
+    mech = sc.Mechanism(c["mech"].to_text())
+    args = to_gpu(torch, c, np.arange(2048))
+    best, times = autotune.tune(mech, *args, use_cache=False, reps=1)
+    assert best["mode"] in ("plain", "static", "persistent") and len(times) == len(autotune.CANDIDATES)
