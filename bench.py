@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--cells", type=int, default=65536)
     ap.add_argument("--mode", default="plain", choices=["plain", "persistent"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
                     help="c2: the headline (default); c3: the uneven batch, queue vs static mapping")
     args = ap.parse_args()
@@ -138,10 +139,56 @@ def main():
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "kernel_ms": kern_s * 1e3, "flops_per_launch": flops},
     }
+    if not args.no_gradient:
+        log("bench: gradient/forward ratio on the 16,384-cell batch")
+        grad = gradient_ratio(sc, torch, mech_text=cells["mech"].to_text(), mode=args.mode)
+        res["config"]["gradient_forward_ratio"] = grad["ratio"]
+        res["gradient"] = grad
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(cells)
     print(json.dumps(res), flush=True)
+
+
+def gradient_ratio(sc, torch, mech_text, mode="plain", reps=3):
+    """Wall time of sc_adjoint (recording forward + reverse sweep with
+    recompute) over that of sc_integrate, same 16,384 cells (53-species
+    mechanism, C2 classes, dt 1e-4 s, seed 204) and options; outputs T1 and
+    Y1 of the {N:1, O:1} species, gradients for T0, Y0 and all dlnA."""
+    from synth.cells import make_cells
+    c = make_cells("C4")
+    dev = "cuda:0"
+    T = torch.tensor(c["T"], device=dev)
+    p = torch.tensor(c["p"], device=dev)
+    Y = torch.tensor(np.ascontiguousarray(c["Y"].T), device=dev)
+    dt = torch.tensor(c["dt"], device=dev)
+    mech = sc.Mechanism(mech_text)
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, mode=mode)
+    k_no = next(k for k, s_ in enumerate(c["mech"].species) if s_.comp == {"N": 1, "O": 1})
+    gT1 = torch.ones_like(T)
+    gY1 = torch.zeros_like(Y)
+    gY1[k_no] = 1.0
+    out = plan.integrate(T, p, Y, dt)
+    cost = out["n_acc"] + out["n_rej"]
+    r = plan.adjoint(T, p, Y, dt, gT1, gY1, cost=cost)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        ms = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ms))
+
+    fwd = timed(lambda: plan.integrate(T, p, Y, dt, out=out))
+    adj = timed(lambda: plan.adjoint(T, p, Y, dt, gT1, gY1, cost=cost))
+    st = r["status"].cpu().numpy()
+    return {"ratio": adj / fwd, "forward_ms": fwd, "adjoint_ms": adj, "cells": int(T.numel()),
+            "failed_cells": int(np.sum(st != 0)), "peak_workspace_bytes": int(r["peak_bytes"]),
+            "g_dlnA_finite": bool(torch.isfinite(r["g_dlnA"]).all().item())}
 
 
 def bench_uneven(args):

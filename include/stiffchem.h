@@ -73,12 +73,18 @@ typedef struct {
     double rtol;        /* relative tolerance (default 1e-6) */
     double atol;        /* absolute tolerance, every component (default 1e-12) */
     int32_t max_steps;  /* accepted + rejected steps per cell (default 100000) */
-    int32_t mode;       /* SC_MODE_PLAIN or SC_MODE_PERSISTENT */
+    int32_t mode;       /* SC_MODE_PLAIN, SC_MODE_PERSISTENT or SC_MODE_STATIC */
     int32_t tile;       /* persistent mode: cells per queue pull (default 1) */
     int32_t grid;       /* persistent/static modes: workgroups; 0 = resident capacity */
     int32_t order;      /* persistent mode: SC_ORDER_* (sorting needs a workspace
                            that sc_integrate allocates on first use) */
-    int32_t reserved;
+    int32_t fixed_step; /* 0: error-controlled steps (default); 1: steps of exactly
+                           h_io[c] (h0[c] for sc_adjoint), the last one shortened to
+                           end at dt, all accepted, no error control (h_io required) */
+    double hmax_frac;   /* > 0: no step longer than hmax_frac * dt[c] (default 0: no
+                           cap).  Error control sees only the state; a cap makes the
+                           steps also resolve how perturbations relax, which the
+                           adjoint's gradients then follow (see sc_adjoint) */
 } sc_options;
 
 typedef struct {
@@ -139,11 +145,68 @@ sc_status sc_linsolve(sc_plan *plan, int64_t n, const double *T, const double *p
  *        h_io[n] or NULL (initial step; the last accepted step is written back)
  *   out: T1[n], Y1[N*ld] (may alias T0/Y0), cell_status[n],
  *        n_acc[n], n_rej[n] (NULL allowed)
- * Options come from the plan (rtol, atol, max_steps, mode, tile, grid). */
+ * Options come from the plan (rtol, atol, max_steps, mode, tile, grid, order,
+ * fixed_step, hmax_frac). */
 sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0,
                        int64_t ld, const double *dt, const double *dlnA, double *h_io, double *T1,
                        double *Y1, int32_t *cell_status, int32_t *n_acc, int32_t *n_rej,
                        void *hip_stream);
+
+/* Vector-Jacobian product of the right-hand side (the transpose of the
+ * sc_jacobian matrix applied to a weight): for every cell
+ *   g = J(y)^T w,  with w = (wY[k*ld + c] for k < N, wT[c]) and the output
+ *   in the same layout (gY, gT);
+ * and, when g_dlnA_cell is not NULL, the parameter part
+ *   g_dlnA_cell[j*n + c] = sum_i w_i d f_i / d dlnA_j
+ * (dlnA_j multiplies the whole net rate of reaction j, forward and reverse
+ * together, so this is q_j times the weight of reaction j's production
+ * terms).  The building block of sc_adjoint (paper Sec. 2.5: analytical
+ * Jacobian of the chemical source term), exposed for testing. */
+sc_status sc_vjp(sc_plan *plan, int64_t n, const double *T, const double *p, const double *Y, int64_t ld,
+                 const double *dlnA, const double *wT, const double *wY, double *gT, double *gY,
+                 double *g_dlnA_cell, void *hip_stream);
+
+/* Discrete adjoint of sc_integrate: the vector-Jacobian product of the map
+ * (T0, Y0, dlnA) -> (T1, Y1) that the integrator computes, with its
+ * accepted step sequence held fixed (the step-size controller is not
+ * differentiated).  Gradients of the integrated source terms with respect to
+ * the initial state and the rate constants (paper Sec. 2.1, Eqs. 3-4: the
+ * sources come from the per-cell integration).
+ *   in : the sc_integrate inputs (T0, p, Y0, ld, dt, dlnA; h0 = initial step
+ *        per cell or NULL, read only) and the cotangents gT1[n], gY1[N*ld];
+ *        cost[n] or NULL: predicted work per cell (e.g. the forward call's
+ *        n_acc + n_rej), cells are then scheduled longest first;
+ *        budget_bytes: device workspace cap (0 = 8 GiB).
+ *   out: gT0[n], gY0[N*ld] (may alias gT1/gY1); g_dlnA[R] (sum over cells)
+ *        or NULL; g_dlnA_cell[R*n] (layout [j*n + c]) or NULL; T1, Y1 (the
+ *        recording pass's end state, identical to sc_integrate's) or NULL;
+ *        cell_status[n]; n_acc[n] or NULL; *peak_bytes (workspace used) or
+ *        NULL.
+ * Each cell is integrated forward once more (recording step sizes and
+ * checkpoints), then reversed step by step: every step is replayed from the
+ * nearest stored state (a segment is recomputed from its checkpoint when not
+ * every state fits), the stage equations are transposed (solves with the
+ * step's own factors, J^T products at the stage points) and the derivative
+ * of the iteration matrix contributes the second-order terms (exact
+ * directional derivatives of J^T w).  The gradients are those of the
+ * discrete map: where the controller takes steps much longer than the
+ * relaxation times of a perturbed direction (a cell at equilibrium takes
+ * one step), they differ from the continuous sensitivities by the method's
+ * damping error for that direction; hmax_frac bounds the step and with it
+ * that difference.  A cell whose integration fails gets its status and NaN
+ * gradients (so g_dlnA is NaN).
+ * The library sizes its per-wave workspace from max_steps; fewer waves run
+ * when the budget is small; SC_EBUDGET if one wave does not fit.  The sum
+ * over cells is taken in a fixed order: results do not depend on the
+ * schedule. */
+sc_status sc_adjoint(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0, int64_t ld,
+                     const double *dt, const double *dlnA, const double *h0, const double *gT1, const double *gY1,
+                     double *gT0, double *gY0, double *g_dlnA, double *g_dlnA_cell, const int32_t *cost,
+                     double *T1, double *Y1, int32_t *cell_status, int32_t *n_acc, size_t budget_bytes,
+                     size_t *peak_bytes, void *hip_stream);
+
+/* Bytes of adjoint workspace per resident wave for the plan's max_steps. */
+size_t sc_adjoint_slot_bytes(const sc_plan *plan);
 
 /* Last error message of the calling thread (valid until its next call). */
 const char *sc_last_error(void);

@@ -35,7 +35,7 @@ class StiffchemError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32),
                 ("mode", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32),
-                ("order", C.c_int32), ("reserved", C.c_int32)]
+                ("order", C.c_int32), ("fixed_step", C.c_int32), ("hmax_frac", C.c_double)]
 
 
 class MechInfo(C.Structure):
@@ -72,8 +72,13 @@ def lib():
         L.sc_jacobian.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P]
         L.sc_linsolve.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P]
         L.sc_integrate.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.sc_vjp.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]
+        L.sc_adjoint.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                 _P, _P, _P, _P, C.c_size_t, C.POINTER(C.c_size_t), _P]
+        L.sc_adjoint_slot_bytes.argtypes = [_P]
+        L.sc_adjoint_slot_bytes.restype = C.c_size_t
         for f in ("sc_mech_load", "sc_mech_info_get", "sc_species_index", "sc_plan_create", "sc_rhs",
-                  "sc_jacobian", "sc_linsolve", "sc_integrate"):
+                  "sc_jacobian", "sc_linsolve", "sc_integrate", "sc_vjp", "sc_adjoint"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -132,7 +137,7 @@ class Plan:
     """A mechanism on one device with integration options."""
 
     def __init__(self, mech: Mechanism, device: int = 0, rtol=1e-6, atol=1e-12, max_steps=100000,
-                 mode="plain", tile=1, grid=0, order="none"):
+                 mode="plain", tile=1, grid=0, order="none", fixed_step=False, hmax_frac=0.0):
         import torch
         self.torch = torch
         self.mech = mech
@@ -141,6 +146,8 @@ class Plan:
         lib().sc_default_options(C.byref(opt))
         opt.rtol, opt.atol, opt.max_steps = rtol, atol, max_steps
         opt.mode, opt.tile, opt.grid, opt.order = MODES[mode], tile, grid, ORDERS[order]
+        opt.fixed_step = 1 if fixed_step else 0
+        opt.hmax_frac = float(hmax_frac)
         self.config = dict(mode=mode, tile=tile, grid=grid, order=order)
         self.options = opt
         h = _P()
@@ -229,6 +236,106 @@ class Plan:
         if hio is not None:
             out["h"] = hio
         return out
+
+    def vjp(self, T, p, Y, wT, wY, dlnA=None, per_cell=False):
+        """J(y)^T w per cell; returns (gT, gY) and, with per_cell, the
+        parameter part [R, n]."""
+        T, p, Y, n = self._state(T, p, Y)
+        d = self._dlnA(dlnA)
+        wT, wY = self._dev(wT), self._dev(wY)
+        if wT.shape != T.shape or wY.shape != Y.shape:
+            raise ValueError("w must have the shape of the state")
+        gT, gY = self.torch.empty_like(T), self.torch.empty_like(Y)
+        gc = self.torch.empty((self.mech.R, n), dtype=self.torch.float64, device=T.device) if per_cell else None
+        _check(lib().sc_vjp(self._h, n, _ptr(T), _ptr(p), _ptr(Y), n, _ptr(d), _ptr(wT), _ptr(wY), _ptr(gT),
+                            _ptr(gY), _ptr(gc), _stream(self.torch, self.device)))
+        return (gT, gY, gc) if per_cell else (gT, gY)
+
+    def adjoint(self, T0, p, Y0, dt, gT1, gY1, dlnA=None, h=None, cost=None, per_cell=False, budget=0,
+                forward_out=False):
+        """Discrete adjoint of integrate(): gradients of <gT1, T1> + <gY1, Y1>
+        with respect to T0, Y0 and dlnA, the accepted step sequence frozen.
+        Returns a dict with gT0, gY0, g_dlnA [R], status, n_acc, peak_bytes and,
+        when asked, g_dlnA_cell [R, n] and the recorded forward T1, Y1."""
+        t = self.torch
+        T0, p, Y0, n = self._state(T0, p, Y0)
+        dt = self._dev(dt)
+        if dt.dim() == 0:
+            dt = dt.expand(n).contiguous()
+        d = self._dlnA(dlnA)
+        gT1, gY1 = self._dev(gT1), self._dev(gY1)
+        if gT1.shape != T0.shape or gY1.shape != Y0.shape:
+            raise ValueError("cotangents must have the shape of the state")
+        h0 = None if h is None else self._dev(h)
+        cst = None if cost is None else self._dev(cost, t.int32)
+        dev = T0.device
+        out = dict(gT0=t.empty_like(T0), gY0=t.empty_like(Y0),
+                   g_dlnA=t.empty(self.mech.R, dtype=t.float64, device=dev),
+                   status=t.empty(n, dtype=t.int32, device=dev), n_acc=t.empty(n, dtype=t.int32, device=dev))
+        gc = t.empty((self.mech.R, n), dtype=t.float64, device=dev) if per_cell else None
+        T1 = t.empty_like(T0) if forward_out else None
+        Y1 = t.empty_like(Y0) if forward_out else None
+        peak = C.c_size_t(0)
+        _check(lib().sc_adjoint(self._h, n, _ptr(T0), _ptr(p), _ptr(Y0), n, _ptr(dt), _ptr(d), _ptr(h0),
+                                _ptr(gT1), _ptr(gY1), _ptr(out["gT0"]), _ptr(out["gY0"]), _ptr(out["g_dlnA"]),
+                                _ptr(gc), _ptr(cst), _ptr(T1), _ptr(Y1), _ptr(out["status"]), _ptr(out["n_acc"]),
+                                budget, C.byref(peak), _stream(t, self.device)))
+        out["peak_bytes"] = peak.value
+        if per_cell:
+            out["g_dlnA_cell"] = gc
+        if forward_out:
+            out["T"], out["Y"] = T1, Y1
+        return out
+
+    def adjoint_slot_bytes(self) -> int:
+        return lib().sc_adjoint_slot_bytes(self._h)
+
+
+def _chem_integrate_fn():
+    import torch
+
+    class ChemIntegrate(torch.autograd.Function):
+        """(T0, Y0, dlnA) -> (T1, Y1) through sc_integrate; backward through
+        sc_adjoint (recording forward + reverse sweep: nothing is stored at
+        forward time beyond the inputs).  p, dt and the plan are constants.
+        Y is [N, n] species-major."""
+
+        @staticmethod
+        def forward(ctx, T0, Y0, dlnA, p, dt, plan, h=None):
+            out = plan.integrate(T0, p, Y0, dt, dlnA=dlnA, h=h)
+            if not bool((out["status"] == 0).all()):
+                bad = int((out["status"] != 0).sum())
+                raise StiffchemError(SC_OK, f"{bad} cells failed to integrate")
+            ctx.plan = plan
+            ctx.h = None if h is None else plan._dev(h)
+            ctx.save_for_backward(T0, Y0, dlnA if dlnA is not None else T0.new_zeros(0), p, dt,
+                                  out["n_acc"] + out["n_rej"])
+            ctx.has_dlnA = dlnA is not None
+            return out["T"], out["Y"]
+
+        @staticmethod
+        def backward(ctx, gT1, gY1):
+            T0, Y0, dlnA, p, dt, cost = ctx.saved_tensors
+            plan = ctx.plan
+            gT1 = torch.zeros_like(T0) if gT1 is None else gT1.contiguous()
+            gY1 = torch.zeros_like(Y0) if gY1 is None else gY1.contiguous()
+            r = plan.adjoint(T0, p, Y0, dt, gT1, gY1, dlnA=dlnA if ctx.has_dlnA else None, h=ctx.h, cost=cost)
+            g_d = r["g_dlnA"] if ctx.has_dlnA and ctx.needs_input_grad[2] else None
+            return r["gT0"], r["gY0"], g_d, None, None, None, None
+
+    return ChemIntegrate
+
+
+_CHEM = None
+
+
+def chem_integrate(T0, Y0, dlnA, p, dt, plan, h=None):
+    """Differentiable integration: returns (T1, Y1); gradients flow to T0, Y0
+    and dlnA (a tensor of R log multipliers, or None)."""
+    global _CHEM
+    if _CHEM is None:
+        _CHEM = _chem_integrate_fn()
+    return _CHEM.apply(T0, Y0, dlnA, p, dt, plan, h)
 
 
 class Chain:

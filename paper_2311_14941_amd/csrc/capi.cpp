@@ -29,6 +29,11 @@ struct sc_plan {
     int capacity = 0;
     void *order_ws = nullptr;  // cell-ordering workspace (grown on demand)
     size_t order_ws_bytes = 0;
+    int adj_capacity = 0;        // resident waves of the adjoint kernel
+    void *adj_ws = nullptr;      // adjoint per-wave slots (grown on demand)
+    size_t adj_ws_bytes = 0;
+    void *gcell_ws = nullptr;    // per-cell parameter adjoints when the caller passes none
+    size_t gcell_ws_bytes = 0;
 };
 
 namespace {
@@ -66,9 +71,10 @@ void release(sc_plan *p)
     (void)hipSetDevice(p->device);
     for (void *d : p->allocs) (void)hipFree(d);
     p->allocs.clear();
-    if (p->order_ws) (void)hipFree(p->order_ws);
-    p->order_ws = nullptr;
-    p->order_ws_bytes = 0;
+    for (void **w : {&p->order_ws, &p->adj_ws, &p->gcell_ws})
+        if (*w) (void)hipFree(*w);
+    p->order_ws = p->adj_ws = p->gcell_ws = nullptr;
+    p->order_ws_bytes = p->adj_ws_bytes = p->gcell_ws_bytes = 0;
     (void)hipSetDevice(cur);
 }
 
@@ -84,6 +90,23 @@ struct DeviceGuard {
         if (ok) (void)hipSetDevice(prev);
     }
 };
+
+// Grow a plan-owned device workspace to at least `need` bytes.
+hipError_t grow(void **ws, size_t *have, size_t need)
+{
+    if (*have >= need) return hipSuccess;
+    if (*ws) (void)hipFree(*ws);
+    *ws = nullptr;
+    *have = 0;
+    hipError_t e = hipMalloc(ws, need);
+    if (e == hipSuccess) *have = need;
+    return e;
+}
+
+scdev::Opts dev_opts(const sc_options &o)
+{
+    return scdev::Opts{o.rtol, o.atol, o.hmax_frac, o.max_steps, o.fixed_step};
+}
 
 sc_status check_common(sc_plan *plan, int64_t n, int64_t ld, std::initializer_list<const void *> ptrs)
 {
@@ -191,6 +214,8 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
     if (o.order < SC_ORDER_NONE || o.order > SC_ORDER_COST) return fail(SC_EINVAL, "unknown cell order");
     if (o.tile <= 0) o.tile = 1;
     if (o.grid < 0) return fail(SC_EINVAL, "grid must be >= 0");
+    if (o.fixed_step != 0 && o.fixed_step != 1) return fail(SC_EINVAL, "fixed_step must be 0 or 1");
+    if (!(o.hmax_frac >= 0.0) || !std::isfinite(o.hmax_frac)) return fail(SC_EINVAL, "hmax_frac must be >= 0");
     DeviceGuard g(device);
     if (!g.ok) return fail(SC_EHIP, "hipSetDevice failed");
     sc_plan *p = nullptr;
@@ -273,6 +298,7 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
         return fail(SC_ENOMEM, "device allocation/upload failed");
     }
     p->capacity = scdev::persistent_capacity(p->np, device);
+    p->adj_capacity = scdev::adjoint_capacity(p->np, d.R, device);
     *out = p;
     return SC_OK;
 }
@@ -321,8 +347,9 @@ sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double 
 {
     sc_status s = check_common(plan, n, ld, {T0, p, Y0, dt, T1, Y1, cell_status});
     if (s != SC_OK || n == 0) return s;
+    if (plan->opt.fixed_step && !h_io) return fail(SC_EINVAL, "fixed_step needs h_io (the step of each cell)");
     DeviceGuard g(plan->device);
-    scdev::Opts o{plan->opt.rtol, plan->opt.atol, plan->opt.max_steps};
+    const scdev::Opts o = dev_opts(plan->opt);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (plan->opt.mode == SC_MODE_PERSISTENT) {
@@ -355,6 +382,94 @@ sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double 
                                     n_acc, n_rej, st);
     }
     return e == hipSuccess ? SC_OK : hip_fail(e, "integrate launch");
+}
+
+sc_status sc_vjp(sc_plan *plan, int64_t n, const double *T, const double *p, const double *Y, int64_t ld,
+                 const double *dlnA, const double *wT, const double *wY, double *gT, double *gY,
+                 double *g_dlnA_cell, void *stream)
+{
+    sc_status s = check_common(plan, n, ld, {T, p, Y, wT, wY, gT, gY});
+    if (s != SC_OK || n == 0) return s;
+    DeviceGuard g(plan->device);
+    hipError_t e = scdev::launch_vjp(plan->np, plan->dm, n, T, p, Y, ld, dlnA, wT, wY, gT, gY, g_dlnA_cell,
+                                     (hipStream_t)stream);
+    return e == hipSuccess ? SC_OK : hip_fail(e, "vjp launch");
+}
+
+size_t sc_adjoint_slot_bytes(const sc_plan *plan)
+{
+    if (!plan) return 0;
+    const int64_t hcap = ((int64_t)plan->opt.max_steps + 31) / 32 * 32;
+    const int nck = scdev::adjoint_slot_checkpoints();
+    int64_t kmax = 1;
+    while ((int64_t)nck * kmax < plan->opt.max_steps) kmax *= 2;
+    return sizeof(double) * (size_t)(hcap + (int64_t)(nck + kmax - 1) * 64);
+}
+
+sc_status sc_adjoint(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0, int64_t ld,
+                     const double *dt, const double *dlnA, const double *h0, const double *gT1, const double *gY1,
+                     double *gT0, double *gY0, double *g_dlnA, double *g_dlnA_cell, const int32_t *cost,
+                     double *T1, double *Y1, int32_t *cell_status, int32_t *n_acc, size_t budget_bytes,
+                     size_t *peak_bytes, void *stream)
+{
+    if (peak_bytes) *peak_bytes = 0;
+    sc_status s = check_common(plan, n, ld, {T0, p, Y0, dt, gT1, gY1, gT0, gY0, cell_status});
+    if (s != SC_OK) return s;
+    const int R = plan->dm.R;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceGuard g(plan->device);
+    if (n == 0) {
+        if (g_dlnA && R > 0) {  // an empty sum: zeros, written by a kernel
+            hipError_t e = scdev::launch_sum_cells(nullptr, 0, R, g_dlnA, st);
+            if (e != hipSuccess) return hip_fail(e, "clear g_dlnA");
+        }
+        return SC_OK;
+    }
+    if (plan->opt.fixed_step && !h0) return fail(SC_EINVAL, "fixed_step needs h0 (the step of each cell)");
+    if (budget_bytes == 0) budget_bytes = (size_t)8 << 30;
+    const scdev::Opts o = dev_opts(plan->opt);
+    // per-cell parameter adjoints: the caller's array, else a plan workspace
+    double *gcell = g_dlnA_cell;
+    size_t used = 0;
+    const size_t gcell_bytes = sizeof(double) * (size_t)R * (size_t)n;
+    if (!gcell && g_dlnA && R > 0) used += gcell_bytes;
+    const size_t slot = sc_adjoint_slot_bytes(plan);
+    if (used + slot > budget_bytes)
+        return fail(SC_EBUDGET, "adjoint workspace of one wave (" + std::to_string(slot) +
+                                    " bytes) exceeds the budget; lower max_steps or raise the budget");
+    int grid = plan->adj_capacity > 0 ? plan->adj_capacity : 1;
+    if (plan->opt.grid > 0 && plan->opt.grid < grid) grid = plan->opt.grid;
+    if (grid > n) grid = (int)n;
+    const size_t fit = (budget_bytes - used) / slot;
+    if ((size_t)grid > fit) grid = (int)fit;
+    hipError_t e = grow(&plan->adj_ws, &plan->adj_ws_bytes, slot * (size_t)grid);
+    if (e != hipSuccess) return hip_fail(e, "adjoint workspace");
+    used += slot * (size_t)grid;
+    if (!gcell && g_dlnA && R > 0) {
+        e = grow(&plan->gcell_ws, &plan->gcell_ws_bytes, gcell_bytes);
+        if (e != hipSuccess) return hip_fail(e, "parameter-adjoint workspace");
+        gcell = static_cast<double *>(plan->gcell_ws);
+    }
+    int32_t *perm = nullptr;
+    if (cost) {
+        e = scdev::order_cells(SC_ORDER_COST, n, dt, cost, nullptr, &plan->order_ws, &plan->order_ws_bytes, &perm,
+                               st);
+        if (e != hipSuccess) return hip_fail(e, "cell ordering");
+        used += plan->order_ws_bytes;
+    }
+    e = scdev::launch_zero_u64(plan->queue, st);
+    if (e != hipSuccess) return hip_fail(e, "queue reset");
+    const int64_t hcap = ((int64_t)plan->opt.max_steps + 31) / 32 * 32;
+    e = scdev::launch_adjoint(plan->np, plan->dm, o, n, T0, p, Y0, ld, dt, dlnA, h0, gT1, gY1, gT0, gY0, gcell,
+                              cell_status, n_acc, T1, Y1, static_cast<double *>(plan->adj_ws),
+                              (int64_t)(slot / sizeof(double)), (int)hcap, plan->queue, perm, grid, st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    if (g_dlnA && R > 0) {
+        e = scdev::launch_sum_cells(gcell, n, R, g_dlnA, st);
+        if (e != hipSuccess) return hip_fail(e, "parameter-adjoint reduction");
+    }
+    if (peak_bytes) *peak_bytes = used;
+    return SC_OK;
 }
 
 }  // extern "C"

@@ -47,7 +47,9 @@ struct DevMech {
 
 struct Opts {
     double rtol, atol;
+    double hmax_frac;  // > 0: steps capped at hmax_frac * dt
     int max_steps;
+    int fixed;  // 1: fixed steps of the caller's h, no error control
 };
 
 hipError_t launch_rhs(int np, const DevMech &m, int64_t n, const double *T, const double *p, const double *Y,
@@ -74,6 +76,19 @@ hipError_t order_cells(int order, int64_t n, const double *dt, const int32_t *na
                        void **ws, size_t *ws_bytes, int32_t **perm, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
 int persistent_capacity(int np, int device);
+
+// adjoint (adjoint.hip)
+hipError_t launch_vjp(int np, const DevMech &m, int64_t n, const double *T, const double *p, const double *Y,
+                      int64_t ld, const double *dlnA, const double *wT, const double *wY, double *gT, double *gY,
+                      double *gcell, hipStream_t s);
+hipError_t launch_adjoint(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0, const double *p,
+                          const double *Y0, int64_t ld, const double *dt, const double *dlnA, const double *h_in,
+                          const double *gT1, const double *gY1, double *gT0, double *gY0, double *gcell,
+                          int32_t *st, int32_t *na, double *T1, double *Y1, double *scratch, int64_t slot_doubles,
+                          int hcap, unsigned long long *queue, const int32_t *perm, int grid, hipStream_t s);
+hipError_t launch_sum_cells(const double *g, int64_t n, int R, double *out, hipStream_t s);
+int adjoint_capacity(int np, int R, int device);
+int adjoint_slot_checkpoints();
 size_t lds_bytes_for(int np);
 
 }  // namespace scdev

@@ -1,0 +1,71 @@
+"""Fixed-step Rosenbrock map on the CPU (test infrastructure).
+
+The device integrator's step formula in transformed form,
+    M u_i = f(y + sum_{j<i} a_ij u_j) + sum_{j<i} (c_ij / h) u_j,
+    M = I/(gamma h) - J(y),   y_new = y + sum_i m_i u_i,
+with the order-4 tableau of tableau.ros4() (stage 4 reuses the stage-3
+function value), evaluated here with the oracle's right-hand side and its
+complex-step Jacobian and dense numpy solves.  With the step sequence fixed
+the map is a smooth function of (y0, dlnA), so central differences of it are
+the reference for the device's discrete adjoint, and its value the
+reference for the device's fixed-step integration.
+"""
+import numpy as np
+
+from paper_2311_14941_amd.tableau import ros4
+
+_TAB = ros4()
+
+
+def step(o, y, p, h, dlnA=None):
+    t = _TAB
+    n = y.size
+    M = np.eye(n) / (t["gamma"] * h) - o.jac_cs(y, p, dlnA=dlnA)
+    U, F = [], {}
+    F[0] = o.rhs(y, p, dlnA=dlnA)
+    for i in range(t["stages"]):
+        r = t["reuse"][i]
+        if r < 0:
+            F[i] = o.rhs(y + sum(t["a"][i, j] * U[j] for j in range(i)), p, dlnA=dlnA)
+            fi = F[i]
+        else:
+            fi = F[r]
+        rhs = fi + sum((t["c"][i, j] / h) * U[j] for j in range(i))
+        U.append(np.linalg.solve(M, rhs))
+    return y + sum(t["m"][i] * U[i] for i in range(t["stages"]))
+
+
+def fixed_map(o, y0, p, dt, h, dlnA=None):
+    """Steps of h from 0 to dt (the last one shortened to end at dt), with the
+    same time bookkeeping as the device controller in fixed mode."""
+    y = np.array(y0, dtype=np.float64)
+    t = 0.0
+    while True:
+        hc, last = h, False
+        if t + hc >= dt:
+            hc, last = dt - t, True
+        y = step(o, y, p, hc, dlnA)
+        t = dt if last else t + hc
+        if last:
+            return y
+
+
+def fd_gradient(o, y0, p, dt, h, w, dlnA, par_dirs):
+    """Central differences of <w, map(y0, dlnA)>: one entry per state
+    component (step 1e-6 |T| for T, 1e-6 max(|Y_k|, 1e-3) for Y_k: the
+    floor keeps the cancellation error of trace species below 1e-6 of the
+    map's size, and the map is smooth through Y_k = 0) and one per
+    rate-multiplier direction (step 1e-5)."""
+    n = y0.size
+    g = np.empty(n)
+    for k in range(n):
+        e = 1e-6 * (abs(y0[k]) if k == n - 1 else max(abs(y0[k]), 1e-3))
+        yp, ym = y0.copy(), y0.copy()
+        yp[k] += e
+        ym[k] -= e
+        g[k] = (w @ fixed_map(o, yp, p, dt, h, dlnA) - w @ fixed_map(o, ym, p, dt, h, dlnA)) / (2 * e)
+    gp = np.empty(len(par_dirs))
+    for q, d in enumerate(par_dirs):
+        e = 1e-5
+        gp[q] = (w @ fixed_map(o, y0, p, dt, h, dlnA + e * d) - w @ fixed_map(o, y0, p, dt, h, dlnA - e * d)) / (2 * e)
+    return g, gp

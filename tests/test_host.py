@@ -164,7 +164,7 @@ def test_order4_tableau_conditions_and_order():
 
 def test_device_tableau_matches_derivation():
     """The constants compiled into the kernels equal the derived order-4 tableau."""
-    src = open(os.path.join(ROOT, "paper_2311_14941_amd", "csrc", "kernels.hip")).read()
+    src = open(os.path.join(ROOT, "paper_2311_14941_amd", "csrc", "core.hpp")).read()
     t = tableau.ros4()
     num = lambda s: [float(x) for x in re.findall(r"-?[0-9]+\.[0-9]+(?:e-?[0-9]+)?", s)]
     TA = num(re.search(r"TA\[NS\]\[NS\] = \{(.*?)\};", src, re.S).group(1))
