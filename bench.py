@@ -65,11 +65,17 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cells", type=int, default=65536)
-    ap.add_argument("--mode", default="plain", choices=["plain", "persistent"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "plain", "persistent", "static"],
+                    help="launch configuration; auto: the autotuner's pick on a 16,384-cell sample")
+    ap.add_argument("--order", default="none", choices=["none", "dt", "cost"],
+                    help="persistent mode: cell order (cost: the previous call's step counts)")
+    ap.add_argument("--tile", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gradient", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
-                    help="c2: the headline (default); c3: the uneven batch, queue vs static mapping")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "copy"],
+                    help="c2: the headline (default); c3: the uneven batch, queue vs static mapping; "
+                         "c5: 20 chained substeps, forward and gradient; copy: a plain device copy of "
+                         "known size (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the batch of independent "
@@ -83,6 +89,10 @@ def main():
     sc.ensure_built()
     if args.workload == "c3":
         return bench_uneven(args)
+    if args.workload == "c5":
+        return bench_chained(args)
+    if args.workload == "copy":
+        return bench_copy(args)
     log("bench: generating C2 workload")
     cells = make_cells("C2")
     n = args.cells
@@ -93,7 +103,16 @@ def main():
     Y = torch.tensor(np.ascontiguousarray(cells["Y"][idx].T), dtype=torch.float64, device=dev)
     dt = torch.tensor(cells["dt"][idx], dtype=torch.float64, device=dev)
     mech = sc.Mechanism(cells["mech"].to_text())
-    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, mode=args.mode)
+    if args.mode == "auto":
+        from paper_2311_14941_amd import autotune
+        log("bench: autotuning the launch configuration on a 16,384-cell sample")
+        s_ = torch.tensor(np.random.default_rng(0).choice(n, 16384, replace=False), device=dev)
+        launch, tune_ms = autotune.tune(mech, T[s_].contiguous(), p[s_].contiguous(), Y[:, s_].contiguous(),
+                                        dt[s_].contiguous(), use_cache=False, reps=1)
+    else:
+        launch = dict(mode=args.mode, tile=args.tile, grid=0, order=args.order)
+        tune_ms = None
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, **launch)
     stream = torch.cuda.current_stream()
     out = None
     log(f"bench: warmup {args.warmup}")
@@ -131,17 +150,30 @@ def main():
         "config": {"workload": "C2: 65,536 reactor cells, seeded 53-species/325-reaction C/H/O/N "
                                "mechanism (30 third-body, 15 Troe), 1-10 atm, T0 300-2400 K in thirds "
                                "(unburnt/near-ignition/equilibrated), dt 1e-4 s, rtol 1e-6, atol 1e-12",
-                   "cells": n, "mode": args.mode, "kernel": "k_integrate<56>",
+                   "cells": n, "launch": launch, "autotune_sample_ms": tune_ms,
+                   "kernel": "k_integrate<56>" if launch["mode"] == "plain" else f"k_integrate_{launch['mode']}<56>",
                    "steps_per_cell_mean": float((nacc + nrej).mean()),
                    "accepted_mean": float(nacc.mean()), "rejected_mean": float(nrej.mean()),
                    "gradient_forward_ratio": None},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(launch),
                      "kernel_ms": kern_s * 1e3, "flops_per_launch": flops},
     }
+    if launch["mode"] != "plain":
+        # the same batch through the plain one-workgroup-per-cell launch, for comparison
+        pp = sc.Plan(mech, rtol=1e-6, atol=1e-12, mode="plain")
+        o2 = pp.integrate(T, p, Y, dt)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        o2 = pp.integrate(T, p, Y, dt, out=o2)
+        b.record(stream)
+        torch.cuda.synchronize()
+        res["config"]["plain_launch_ms"] = a.elapsed_time(b)
+        res["config"]["plain_launch_identical"] = bool(torch.equal(o2["T"], out["T"]) and torch.equal(o2["Y"], out["Y"]))
     if not args.no_gradient:
         log("bench: gradient/forward ratio on the 16,384-cell batch")
-        grad = gradient_ratio(sc, torch, mech_text=cells["mech"].to_text(), mode=args.mode)
+        grad = gradient_ratio(sc, torch, mech_text=cells["mech"].to_text(), launch=launch)
         res["config"]["gradient_forward_ratio"] = grad["ratio"]
         res["gradient"] = grad
     if not args.no_cpu_baseline:
@@ -150,7 +182,123 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def gradient_ratio(sc, torch, mech_text, mode="plain", reps=3):
+KERNEL_SOURCES = ("paper_2311_14941_amd/csrc/core.hpp", "paper_2311_14941_amd/csrc/kernels.hip",
+                  "paper_2311_14941_amd/csrc/devmech.hpp")
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launch):
+    """HBM bytes per launch of the integration kernel from the committed
+    counter runs (profiles/k_integrate_c2_traffic.json: FETCH_SIZE and
+    WRITE_SIZE of the kernel, each divided by the bytes-per-byte ratio the
+    same counter reads for a plain copy of known size), or None when the
+    kernel sources changed since those runs or they cover another launch
+    configuration."""
+    path = os.path.join(ROOT, "profiles", "k_integrate_c2_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_digest") != kernel_digest() or t.get("launch") != launch:
+        return None
+    return t["traffic_bytes"]
+
+
+def bench_copy(args):
+    """A plain device copy of 2^27 doubles (1 GiB read + 1 GiB written),
+    timed; under rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE per dispatch
+    give the counters' bytes per true byte."""
+    import torch
+    n = 1 << 27
+    src = torch.arange(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    nbytes = n * 8
+    print(json.dumps({"metric": "device copy", "bytes_read": nbytes, "bytes_written": nbytes, "ms": ms,
+                      "GB/s": 2 * nbytes / ms / 1e6, "steps": args.steps}), flush=True)
+
+
+def bench_chained(args):
+    """20 chained substeps of 5e-5 s over 65,536 cells (53-species
+    mechanism, C2 classes, seed 205), the state and step size carried:
+    forward as one captured HIP graph, and the gradient of the final T and
+    Y1 of the {N:1, O:1} species through torch.autograd (20 sc_integrate
+    calls forward, 20 sc_adjoint calls backward).  Reports both times, their
+    ratio and the device memory held."""
+    import torch
+    import paper_2311_14941_amd as sc
+    from synth.cells import make_cells
+    log("bench: generating the chained-substep batch")
+    c = make_cells("C5s")
+    nsub = c["substeps"]
+    dev = "cuda:0"
+    T = torch.tensor(c["T"], device=dev)
+    p = torch.tensor(c["p"], device=dev)
+    Y = torch.tensor(np.ascontiguousarray(c["Y"].T), device=dev)
+    dt = torch.tensor(c["dt"], device=dev)
+    mech = sc.Mechanism(c["mech"].to_text())
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12)
+    k_no = next(k for k, s_ in enumerate(c["mech"].species) if s_.comp == {"N": 1, "O": 1})
+    log("bench: capture + forward")
+    chain = sc.Chain(plan, T, p, Y, dt, nsub)
+    chain.run(T, Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Tf, Yf, _, steps = chain.run(T, Y)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 1e3
+    log("bench: gradient through autograd")
+    torch.cuda.reset_peak_memory_stats()
+    free0, total = torch.cuda.mem_get_info()
+    T0 = T.clone().requires_grad_(True)
+    Y0 = Y.clone().requires_grad_(True)
+    dl = torch.zeros(mech.R, dtype=torch.float64, device=dev, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Tk, Yk, h = T0, Y0, None
+    for _ in range(nsub):
+        Tk, Yk, h = sc.chem_integrate(Tk, Yk, dl, p, dt, plan, h=h)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss = Tk.sum() + Yk[k_no].sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    free1, _ = torch.cuda.mem_get_info()
+    same = bool(torch.equal(Tk.detach(), Tf) and torch.equal(Yk.detach(), Yf))
+    line = {"metric": "chained substeps: forward and gradient wall time", "unit": "ms",
+            "value": (t2 - t1) * 1e3 / fwd_ms, "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "65,536 cells, 53-species mechanism, C2 classes, 20 chained substeps of "
+                                   "5e-5 s (state and step size carried), rtol 1e-6", "substeps": nsub},
+            "forward_graph_ms": fwd_ms, "autograd_forward_ms": (t1 - t0) * 1e3,
+            "backward_ms": (t2 - t1) * 1e3, "gradient_forward_ratio": (t2 - t1) * 1e3 / fwd_ms,
+            "graph_and_autograd_forward_identical": same,
+            "steps_per_cell_mean": float(steps.double().mean().item()),
+            "torch_peak_bytes": int(torch.cuda.max_memory_allocated()),
+            "device_bytes_in_use_after": int(total - free1), "device_bytes_in_use_before": int(total - free0),
+            "adjoint_slot_bytes": int(plan.adjoint_slot_bytes()),
+            "grad_finite": bool(torch.isfinite(T0.grad).all() and torch.isfinite(dl.grad).all())}
+    print(json.dumps(line), flush=True)
+
+
+def gradient_ratio(sc, torch, mech_text, launch, reps=3):
     """Wall time of sc_adjoint (recording forward + reverse sweep with
     recompute) over that of sc_integrate, same 16,384 cells (53-species
     mechanism, C2 classes, dt 1e-4 s, seed 204) and options; outputs T1 and
@@ -163,7 +311,7 @@ def gradient_ratio(sc, torch, mech_text, mode="plain", reps=3):
     Y = torch.tensor(np.ascontiguousarray(c["Y"].T), device=dev)
     dt = torch.tensor(c["dt"], device=dev)
     mech = sc.Mechanism(mech_text)
-    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, mode=mode)
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, **launch)
     k_no = next(k for k, s_ in enumerate(c["mech"].species) if s_.comp == {"N": 1, "O": 1})
     gT1 = torch.ones_like(T)
     gY1 = torch.zeros_like(Y)

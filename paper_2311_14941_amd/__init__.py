@@ -228,8 +228,8 @@ class Plan:
         if out is None:
             out = dict(T=t.empty_like(T0), Y=t.empty_like(Y0),
                        status=t.empty(n, dtype=t.int32, device=T0.device),
-                       n_acc=t.empty(n, dtype=t.int32, device=T0.device),
-                       n_rej=t.empty(n, dtype=t.int32, device=T0.device))
+                       n_acc=t.zeros(n, dtype=t.int32, device=T0.device),
+                       n_rej=t.zeros(n, dtype=t.int32, device=T0.device))
         _check(lib().sc_integrate(self._h, n, _ptr(T0), _ptr(p), _ptr(Y0), n, _ptr(dt), _ptr(d),
                                   _ptr(hio), _ptr(out["T"]), _ptr(out["Y"]), _ptr(out["status"]),
                                   _ptr(out["n_acc"]), _ptr(out["n_rej"]), _stream(t, self.device)))
@@ -295,31 +295,33 @@ def _chem_integrate_fn():
     import torch
 
     class ChemIntegrate(torch.autograd.Function):
-        """(T0, Y0, dlnA) -> (T1, Y1) through sc_integrate; backward through
-        sc_adjoint (recording forward + reverse sweep: nothing is stored at
-        forward time beyond the inputs).  p, dt and the plan are constants.
-        Y is [N, n] species-major."""
+        """(T0, Y0, dlnA) -> (T1, Y1, h1) through sc_integrate; backward
+        through sc_adjoint (recording forward + reverse sweep: nothing is
+        stored at forward time beyond the inputs).  p, dt, the plan and the
+        initial step h are constants; h1 (the step proposed for a following
+        substep) is not differentiable.  Y is [N, n] species-major."""
 
         @staticmethod
-        def forward(ctx, T0, Y0, dlnA, p, dt, plan, h=None):
-            out = plan.integrate(T0, p, Y0, dt, dlnA=dlnA, h=h)
+        def forward(ctx, T0, Y0, dlnA, p, dt, plan, h):
+            hin = torch.zeros_like(T0) if h is None else plan._dev(h)
+            out = plan.integrate(T0, p, Y0, dt, dlnA=dlnA, h=hin)
             if not bool((out["status"] == 0).all()):
                 bad = int((out["status"] != 0).sum())
-                raise StiffchemError(SC_OK, f"{bad} cells failed to integrate")
+                raise RuntimeError(f"{bad} cells failed to integrate; no gradient is defined for them")
             ctx.plan = plan
-            ctx.h = None if h is None else plan._dev(h)
-            ctx.save_for_backward(T0, Y0, dlnA if dlnA is not None else T0.new_zeros(0), p, dt,
+            ctx.save_for_backward(T0, Y0, dlnA if dlnA is not None else T0.new_zeros(0), p, dt, hin,
                                   out["n_acc"] + out["n_rej"])
             ctx.has_dlnA = dlnA is not None
-            return out["T"], out["Y"]
+            ctx.mark_non_differentiable(out["h"])
+            return out["T"], out["Y"], out["h"]
 
         @staticmethod
-        def backward(ctx, gT1, gY1):
-            T0, Y0, dlnA, p, dt, cost = ctx.saved_tensors
+        def backward(ctx, gT1, gY1, gh1):
+            T0, Y0, dlnA, p, dt, hin, cost = ctx.saved_tensors
             plan = ctx.plan
             gT1 = torch.zeros_like(T0) if gT1 is None else gT1.contiguous()
             gY1 = torch.zeros_like(Y0) if gY1 is None else gY1.contiguous()
-            r = plan.adjoint(T0, p, Y0, dt, gT1, gY1, dlnA=dlnA if ctx.has_dlnA else None, h=ctx.h, cost=cost)
+            r = plan.adjoint(T0, p, Y0, dt, gT1, gY1, dlnA=dlnA if ctx.has_dlnA else None, h=hin, cost=cost)
             g_d = r["g_dlnA"] if ctx.has_dlnA and ctx.needs_input_grad[2] else None
             return r["gT0"], r["gY0"], g_d, None, None, None, None
 
@@ -330,8 +332,10 @@ _CHEM = None
 
 
 def chem_integrate(T0, Y0, dlnA, p, dt, plan, h=None):
-    """Differentiable integration: returns (T1, Y1); gradients flow to T0, Y0
-    and dlnA (a tensor of R log multipliers, or None)."""
+    """Differentiable integration: returns (T1, Y1, h1); gradients flow to T0,
+    Y0 and dlnA (a tensor of R log multipliers, or None).  h: initial step
+    per cell (None: dt); h1 carries the controller's next step to a
+    following substep (operator splitting)."""
     global _CHEM
     if _CHEM is None:
         _CHEM = _chem_integrate_fn()

@@ -12,13 +12,17 @@ INC = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libstiffchem.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["mech.cpp", "capi.cpp", "kernels.hip", "adjoint.hip"]
-HEADERS = ["mech.hpp", "devmech.hpp"]
+HEADERS = ["mech.hpp", "devmech.hpp", "core.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("STIFFCHEM_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every HIP build
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # multiply-adds are fused per source expression only, so every
+         # inlined copy of the step routine (the integrator's, the adjoint's
+         # recording pass and its replays) rounds identically
+         "-ffp-contract=on",
          f"-I{INC}", f"-I{CSRC}"]
 
 

@@ -33,7 +33,7 @@
 namespace scdev {
 
 // Checkpoint slots per cell (even).
-constexpr int NCK = 256;
+constexpr int NCK = 2048;
 
 // LDS of the adjoint: the forward layout followed by the vector-Jacobian
 // product's work vectors, the per-stage adjoint vectors and the per-reaction
@@ -131,25 +131,26 @@ __device__ double vjp(const DevMech &m, double *lds, S y, double p, const double
     return part(g);
 }
 
-// Solve (L U)^T x = b with the factors parked column-major in F (column c
-// contiguous): U^T z = b, then L^T x = z.  Each unknown is a dot product of
-// one stored column with the solved part, so every LDS read is one
-// conflict-free wave access and the sum is a wave reduction.
+// Solve (L U)^T x = b with the factors parked column-major in F: U^T z = b,
+// then L^T x = z.  Each unknown is a dot product of one stored column with
+// the solved part: one contiguous (conflict-free) LDS read per step and a
+// wave reduction.
 template <int NP>
 __device__ double lu_solve_T(const double *F, double dinv, double b, int lane)
 {
+    constexpr int FS = Lds<NP>::PS;
     const int li = lane < NP ? lane : 0;
     double z = 0.0;
 #pragma unroll 2
     for (int k = 0; k < NP; ++k) {
-        const double u = F[k * NP + li];  // U_jk in lane j (j < k)
+        const double u = F[k * FS + li];  // U_jk in lane j (j < k)
         const double s = wave_sum(lane < k ? u * z : 0.0);
         if (lane == k) z = (b - s) * dinv;
     }
     double x = 0.0;
 #pragma unroll 2
     for (int k = NP - 1; k >= 0; --k) {
-        const double l = F[k * NP + li];  // L_jk in lane j (j > k)
+        const double l = F[k * FS + li];  // L_jk in lane j (j > k)
         const double s = wave_sum(lane > k ? l * x : 0.0);
         if (lane == k) x = z - s;
     }

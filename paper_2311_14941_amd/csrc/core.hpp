@@ -52,7 +52,7 @@ static __constant__ double TE[NS] = {0.4092508278871161, -1.0795845833425672, 0.
 // function value of a stage: 0 = f(y) from the Jacobian pass, -1 = evaluate,
 // k > 0 = reuse the value evaluated at stage k (same point)
 static __constant__ int TREUSE[NS] = {0, -1, -1, 2};
-constexpr double ERR_EXP = 1.0 / 4.0;  // 1/(embedded order + 1)
+// step-size exponent 1/(embedded order + 1) = 1/4 (ctl_end takes the fourth root)
 
 constexpr int WAVE = 64;
 // LDS loads issued ahead per group in the unrolled row/solve loops; bounds
@@ -166,8 +166,11 @@ __device__ __forceinline__ void lds_add(double *lds, int i, Dual x, int toff)
 // ---------------------------------------------------------------------------
 template <int NP>
 struct Lds {
-    static constexpr int P = 0;          // NP x NP Jacobian terms, later the LU factors
-    static constexpr int C = NP * NP;    // concentrations
+    // row stride of the Jacobian terms: lanes reading their own rows hit
+    // addresses a stride apart; an odd stride spreads them over the banks
+    static constexpr int PS = NP + 1;
+    static constexpr int P = 0;          // NP x PS Jacobian terms, later the LU factors (stride NP)
+    static constexpr int C = NP * PS;    // concentrations
     static constexpr int G = C + NP;     // g/RT
     static constexpr int H = G + NP;     // h/RT
     static constexpr int WD = H + NP;    // production-rate accumulator
@@ -415,7 +418,7 @@ __device__ __forceinline__ void scatter(const DevMech &m, double *lds, int j, co
         atomicAdd(&lds[Lds<NP>::WD + row], nu * o.q);
         if (JAC) {
             atomicAdd(&lds[Lds<NP>::UA + row], nu * o.euler);
-            double *Prow = P + row * NP;
+            double *Prow = P + row * Lds<NP>::PS;
 #pragma unroll
             for (int s = 0; s < sc::NDEP; ++s)
                 if (use[s]) atomicAdd(&Prow[col[s]], nu * o.d[s]);
@@ -425,8 +428,8 @@ __device__ __forceinline__ void scatter(const DevMech &m, double *lds, int j, co
     if (JAC) {
 #pragma unroll
         for (int s = 0; s < sc::NDEP; ++s)
-            if (use[s]) atomicAdd(&P[N * NP + col[s]], dHJ * o.d[s]);
-        atomicAdd(&P[N * NP + N], dHJ * o.dT);
+            if (use[s]) atomicAdd(&P[N * Lds<NP>::PS + col[s]], dHJ * o.d[s]);
+        atomicAdd(&P[N * Lds<NP>::PS + N], dHJ * o.dT);
     }
 }
 
@@ -474,7 +477,7 @@ __device__ double rhs_jac(const DevMech &m, double *lds, double y, double p, con
     const Mix<> x = mixture<NP>(m, lds, y, p, th, lane);
     if (lane < NP) {
 #pragma unroll 4
-        for (int i = 0; i < NP; ++i) P[i * NP + lane] = 0.0;  // lane c clears column c
+        for (int i = 0; i < NP; ++i) P[i * Lds<NP>::PS + lane] = 0.0;  // lane c clears column c
     }
     wave_sync();
     const double RT = m.Rgas * x.T;
@@ -506,8 +509,9 @@ __device__ double rhs_jac(const DevMech &m, double *lds, double y, double p, con
     // fold the column-dependent parts of the temperature row into P[N][*]:
     // J_Tm = -(1/cp) (1/W_m) (P_Tm + Wbar Eu + fT cp_m),
     // J_TT = -(1/cp) (P_TT/rho + Eu/T + sum cp_k f_k/W_k + fT sum dcp_k Y_k/W_k)
-    if (lane < N) P[N * NP + lane] += x.Wbar * Eu + fT * m.Rgas * th.cpR;
-    if (lane == N) P[N * NP + N] = P[N * NP + N] / x.rho + Eu * x.invT + Scpf + fT * Sdcp;
+    const int PS = Lds<NP>::PS;
+    if (lane < N) P[N * PS + lane] += x.Wbar * Eu + fT * m.Rgas * th.cpR;
+    if (lane == N) P[N * PS + N] = P[N * PS + N] / x.rho + Eu * x.invT + Scpf + fT * Sdcp;
     if (lane < NP) lds[Lds<NP>::IW + lane] = lane < N ? m.invW()[lane] : 0.0;
     wave_sync();
     const double invcp = 1.0 / x.cp;
@@ -528,7 +532,7 @@ __device__ __forceinline__ void jac_row(const DevMech &m, const double *lds, con
                                         double (&a)[NP])
 {
     const int N = m.N;
-    const double *P = lds + Lds<NP>::P + (lane < NP ? lane : 0) * NP;
+    const double *P = lds + Lds<NP>::P + (lane < NP ? lane : 0) * Lds<NP>::PS;
     const double *IW = lds + Lds<NP>::IW;
 #pragma unroll
     for (int c = 0; c < NP; ++c) {
@@ -576,15 +580,15 @@ __device__ __forceinline__ void lu_factor(double (&a)[NP], double &dinv, int lan
     }
 }
 
-// Park the factors in LDS, column-major (F[c*NP + i] = row i, column c), so
-// that every read in the triangular solves is one conflict-free wave access.
+// Park the factors in LDS, column-major (F[c*PS + i] = row i, column c), so
+// that every read in the triangular solves is one contiguous wave access.
 template <int NP>
 __device__ __forceinline__ void store_factors(double *F, const double (&a)[NP], int lane)
 {
     if (lane < NP) {
 #pragma unroll
         for (int c = 0; c < NP; ++c) {
-            F[c * NP + lane] = a[c];
+            F[c * Lds<NP>::PS + lane] = a[c];
             SC_FENCE_EVERY(c);
         }
     }
@@ -597,7 +601,7 @@ __device__ __forceinline__ double lu_solve(const double *F, double dinv, double 
     const int li = lane < NP ? lane : 0;
 #pragma unroll
     for (int k = 0; k < NP - 1; ++k) {
-        const double l = F[k * NP + li];
+        const double l = F[k * Lds<NP>::PS + li];
         const double z = rdlane(b, k);
         if (lane > k) b = fma(-l, z, b);
         SC_FENCE_EVERY(k);
@@ -606,7 +610,7 @@ __device__ __forceinline__ double lu_solve(const double *F, double dinv, double 
     for (int k = NP - 1; k >= 0; --k) {
         if (lane == k) b *= dinv;
         const double z = rdlane(b, k);
-        const double u = F[k * NP + li];
+        const double u = F[k * Lds<NP>::PS + li];
         if (lane < k) b = fma(-u, z, b);
         SC_FENCE_EVERY(NP - 1 - k);
     }
@@ -741,7 +745,10 @@ __device__ __forceinline__ int ctl_end(Ctl &s, const Opts &o, double err, double
         return 0;
     }
     s.nonfinite = 0;
-    double fac = 0.9 * pow(fmax(err, 1e-300), -ERR_EXP);
+    // err^(-1/4) as two correctly rounded square roots: no library pow,
+    // whose simplification depends on the surrounding code, so every
+    // kernel that runs the controller takes the same steps
+    double fac = 0.9 / sqrt(sqrt(fmax(err, 1e-300)));
     fac = fmin(6.0, fmax(0.2, fac));
     if (err <= 1.0) {
         ++s.nacc;

@@ -187,9 +187,9 @@ def test_adjoint_fixed_steps_chon53(torch, sc, oracle_mod):
 
 
 def test_adjoint_segment_recompute(torch, sc, oracle_mod):
-    """600 fixed steps: more than the 256 checkpoint slots, so the recorder
+    """2500 fixed steps: more than the 2048 checkpoint slots, so the recorder
     thins its checkpoints and the reverse sweep recomputes segments."""
-    _fixed_case(torch, sc, oracle_mod, "C1", np.array([11, 700]), 600, 1e-2, npar=3)
+    _fixed_case(torch, sc, oracle_mod, "C1", np.array([700]), 2500, 1e-2, npar=2)
 
 
 def _sens_worst(torch, sc, plan, c, idx, g, N, k_no):
@@ -351,7 +351,7 @@ def test_autograd_function(torch, sc):
     Y0 = Y.clone().requires_grad_(True)
     dlnA = torch.zeros(mech.n_reactions, dtype=torch.float64, device="cuda:0", requires_grad=True)
     k_no = next(k for k, s in enumerate(mech.species) if s.comp == {"N": 1, "O": 1})
-    T1, Y1 = sc.chem_integrate(T0, Y0, dlnA, p, dt, plan)
+    T1, Y1, _ = sc.chem_integrate(T0, Y0, dlnA, p, dt, plan)
     loss = (T1 * 1e-3).sum() + Y1[k_no].sum()
     loss.backward()
     gT1 = torch.full_like(T, 1e-3)
