@@ -82,9 +82,9 @@ __device__ double vjp(const DevMech &m, double *lds, S y, double p, const double
     S bacc = 0.0, tacc = 0.0;
 #pragma unroll 1
     for (int j = lane; j < R; j += WAVE) {
-        const RxRec &rr = m.rx[j];
+        const RxRec rr = load_rec(m, j);
         const double dl = dlnA ? dlnA[rr.orig] : 0.0;
-        const RxOut<S> o = reaction<true, S>(m, lds, j, x, dl, Lds<NP>::C, Lds<NP>::G, Lds<NP>::H, toff);
+        const RxOut<S> o = reaction<true, S>(m, lds, rr, x, dl, Lds<NP>::C, Lds<NP>::G, Lds<NP>::H, toff);
         double sig = 0.0;
 #pragma unroll
         for (int i = 0; i < sc::MAXSIDE; ++i) {

@@ -268,11 +268,19 @@ struct RxOut {
     S dH;            // reaction enthalpy / RT
 };
 
-template <bool JAC, class S = double>
-__device__ __forceinline__ RxOut<S> reaction(const DevMech &m, const double *lds, int j, const Mix<S> &x, double dl,
-                                             int CO, int GO, int HO, int toff = 0)
+// A reaction's record in registers: one burst of wide loads issued together
+// (one memory round trip), so later uses of its fields wait on nothing.
+__device__ __forceinline__ RxRec load_rec(const DevMech &m, int j)
 {
-    const RxRec &rr = m.rx[j];
+    RxRec r;
+    __builtin_memcpy(&r, &m.rx[j], sizeof(RxRec));
+    return r;
+}
+
+template <bool JAC, class S = double>
+__device__ __forceinline__ RxOut<S> reaction(const DevMech &m, const double *lds, const RxRec &rr, const Mix<S> &x,
+                                             double dl, int CO, int GO, int HO, int toff = 0)
+{
     const int kind = rr.kind;
     const int nr = rr.nr, np = rr.np;
     const S lnkinf = rr.lnA + dl + rr.b * x.lnT - rr.EaR * x.invT;
@@ -385,10 +393,9 @@ __device__ __forceinline__ RxOut<S> reaction(const DevMech &m, const double *lds
 // Jacobian pass, the sparse analytical terms of every (row, slot) pair, the
 // temperature column and (weighted by the reaction enthalpy) the temperature row.
 template <int NP, bool JAC>
-__device__ __forceinline__ void scatter(const DevMech &m, double *lds, int j, const RxOut<> &o, double dHJ)
+__device__ __forceinline__ void scatter(const DevMech &m, double *lds, const RxRec &rr, const RxOut<> &o, double dHJ)
 {
     const int N = m.N;
-    const RxRec &rr = m.rx[j];
     const int nr = rr.nr, np = rr.np;
     double *P = lds + Lds<NP>::P;
     int col[sc::NDEP];
@@ -408,11 +415,14 @@ __device__ __forceinline__ void scatter(const DevMech &m, double *lds, int j, co
             col[6 + e] = use[6 + e] ? rr.esp[e] : 0;
         }
     }
-    // rows: reactants then products (a rolled loop keeps one row's terms live)
-#pragma unroll 1
-    for (int r = 0; r < nr + np; ++r) {
-        const bool isr = r < nr;
-        const int ri = isr ? r : r - nr;
+    // rows: reactants then products, unrolled over the slots so that the
+    // record's species and coefficients stay in registers (a rolled loop
+    // indexes them at run time and reloads them from memory every row)
+#pragma unroll
+    for (int r = 0; r < 2 * sc::MAXSIDE; ++r) {
+        const bool isr = r < sc::MAXSIDE;
+        const int ri = isr ? r : r - sc::MAXSIDE;
+        if (ri >= (isr ? nr : np)) continue;
         const int row = isr ? rr.rsp[ri] : rr.psp[ri];
         const double nu = isr ? -(double)rr.rnu[ri] : (double)rr.pnu[ri];
         atomicAdd(&lds[Lds<NP>::WD + row], nu * o.q);
@@ -443,9 +453,10 @@ __device__ double rhs(const DevMech &m, double *lds, double y, double p, const d
     wave_sync();
 #pragma unroll 1
     for (int j = lane; j < R; j += WAVE) {
-        const double dl = dlnA ? dlnA[m.rx[j].orig] : 0.0;
-        const RxOut<> o = reaction<false>(m, lds, j, x, dl, Lds<NP>::C, Lds<NP>::G, Lds<NP>::H);
-        scatter<NP, false>(m, lds, j, o, 0.0);
+        const RxRec rr = load_rec(m, j);
+        const double dl = dlnA ? dlnA[rr.orig] : 0.0;
+        const RxOut<> o = reaction<false>(m, lds, rr, x, dl, Lds<NP>::C, Lds<NP>::G, Lds<NP>::H);
+        scatter<NP, false>(m, lds, rr, o, 0.0);
     }
     wave_sync();
     double f = 0.0, hw = 0.0;
@@ -483,9 +494,10 @@ __device__ double rhs_jac(const DevMech &m, double *lds, double y, double p, con
     const double RT = m.Rgas * x.T;
 #pragma unroll 1
     for (int j = lane; j < R; j += WAVE) {
-        const double dl = dlnA ? dlnA[m.rx[j].orig] : 0.0;
-        const RxOut<> o = reaction<true>(m, lds, j, x, dl, Lds<NP>::C, Lds<NP>::G, Lds<NP>::H);
-        scatter<NP, true>(m, lds, j, o, o.dH * RT);
+        const RxRec rr = load_rec(m, j);
+        const double dl = dlnA ? dlnA[rr.orig] : 0.0;
+        const RxOut<> o = reaction<true>(m, lds, rr, x, dl, Lds<NP>::C, Lds<NP>::G, Lds<NP>::H);
+        scatter<NP, true>(m, lds, rr, o, o.dH * RT);
     }
     wave_sync();
     double f = 0.0, hw = 0.0, eu = 0.0, cpf = 0.0, dcp = 0.0, uk = 0.0, Wk = 0.0;
