@@ -182,8 +182,7 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-KERNEL_SOURCES = ("paper_2311_14941_amd/csrc/core.hpp", "paper_2311_14941_amd/csrc/kernels.hip",
-                  "paper_2311_14941_amd/csrc/devmech.hpp")
+KERNEL_SOURCES = ("paper_2311_14941_amd/csrc/core.hpp", "paper_2311_14941_amd/csrc/kernels.hip")
 
 
 def kernel_digest():
