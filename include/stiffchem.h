@@ -208,6 +208,25 @@ sc_status sc_adjoint(sc_plan *plan, int64_t n, const double *T0, const double *p
 /* Bytes of adjoint workspace per resident wave for the plan's max_steps. */
 size_t sc_adjoint_slot_bytes(const sc_plan *plan);
 
+/* Transport step of an operator-split driver on a uniform 2-D grid of
+ * nx * ny cells (row-major, c = iy*nx + ix), every cell with its own local
+ * time step dt[c] (paper Sec. 2.5: per-cell chemistry between flow steps,
+ * local time stepping).  Not part of the chemistry integration: the cheap
+ * mixing operator that alternates with sc_integrate in a split loop.
+ * For each of ncomp components (rows of ld values, in[k*ld + c]):
+ *   out = q - Co (q - q_west) + Fo (q_east + q_west + q_north + q_south - 4 q),
+ *   Co = u[c] dt[c] / dx (first-order upwind, u >= 0 along +x),
+ *   Fo = diffusivity dt[c] / dx^2,
+ * with the inflow profile inflow[k*ny + iy] west of ix = 0 and zero-gradient
+ * boundaries elsewhere.  With Co + 4 Fo <= 1 (the caller's choice of dt)
+ * every output is a convex combination of inputs: mass fractions stay in
+ * [0, 1] and keep their sum.  out has the layout of in (rows of ld values).
+ * Device pointers; out must not alias in.  SC_EINVAL for non-positive
+ * sizes, ld < nx*ny, NULL arrays, in == out, dx <= 0 or diffusivity < 0. */
+sc_status sc_transport2d(int32_t nx, int32_t ny, int32_t ncomp, const double *in, int64_t ld, const double *u,
+                         const double *dt, double dx, double diffusivity, const double *inflow, double *out,
+                         void *hip_stream);
+
 /* Last error message of the calling thread (valid until its next call). */
 const char *sc_last_error(void);
 

@@ -75,6 +75,9 @@ def lib():
         L.sc_vjp.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]
         L.sc_adjoint.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                  _P, _P, _P, _P, C.c_size_t, C.POINTER(C.c_size_t), _P]
+        L.sc_transport2d.argtypes = [C.c_int32, C.c_int32, C.c_int32, _P, _I64, _P, _P, C.c_double, C.c_double,
+                                     _P, _P, _P]
+        L.sc_transport2d.restype = C.c_int
         L.sc_adjoint_slot_bytes.argtypes = [_P]
         L.sc_adjoint_slot_bytes.restype = C.c_size_t
         for f in ("sc_mech_load", "sc_mech_info_get", "sc_species_index", "sc_plan_create", "sc_rhs",
@@ -289,6 +292,22 @@ class Plan:
 
     def adjoint_slot_bytes(self) -> int:
         return lib().sc_adjoint_slot_bytes(self._h)
+
+
+def transport2d(nx, ny, q, u, dt, dx, diffusivity, inflow, out=None):
+    """One transport step (sc_transport2d) of the rows of q [ncomp, nx*ny]
+    on the nx x ny grid; inflow [ncomp, ny].  Returns out."""
+    import torch
+    if q.dim() != 2 or q.shape[1] != nx * ny or inflow.shape != (q.shape[0], ny):
+        raise ValueError("q must be [ncomp, nx*ny] and inflow [ncomp, ny]")
+    for t in (q, u, dt, inflow):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("transport arrays must be contiguous float64 device tensors")
+    out = torch.empty_like(q) if out is None else out
+    _check(lib().sc_transport2d(nx, ny, q.shape[0], _ptr(q), nx * ny, _ptr(u), _ptr(dt), float(dx),
+                                float(diffusivity), _ptr(inflow), _ptr(out),
+                                _stream(torch, q.device.index or 0)))
+    return out
 
 
 def _chem_integrate_fn():

@@ -472,4 +472,19 @@ sc_status sc_adjoint(sc_plan *plan, int64_t n, const double *T0, const double *p
     return SC_OK;
 }
 
+sc_status sc_transport2d(int32_t nx, int32_t ny, int32_t ncomp, const double *in, int64_t ld, const double *u,
+                         const double *dt, double dx, double diffusivity, const double *inflow, double *out,
+                         void *stream)
+{
+    if (nx <= 0 || ny <= 0 || ncomp <= 0) return fail(SC_EINVAL, "nx, ny and ncomp must be positive");
+    if (ld < (int64_t)nx * ny) return fail(SC_EINVAL, "ld must be >= nx * ny");
+    if (!in || !u || !dt || !inflow || !out) return fail(SC_EINVAL, "required array pointer is NULL");
+    if (in == out) return fail(SC_EINVAL, "out must not alias in");
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(SC_EINVAL, "dx must be positive");
+    if (!(diffusivity >= 0.0) || !std::isfinite(diffusivity)) return fail(SC_EINVAL, "diffusivity must be >= 0");
+    hipError_t e = scdev::launch_transport2d(nx, ny, ncomp, in, ld, u, dt, dx, diffusivity, inflow, out,
+                                             (hipStream_t)stream);
+    return e == hipSuccess ? SC_OK : hip_fail(e, "transport launch");
+}
+
 }  // extern "C"

@@ -88,6 +88,11 @@ hipError_t launch_adjoint(int np, const DevMech &m, const Opts &o, int64_t n, co
                           int hcap, unsigned long long *queue, const int32_t *perm, int grid, hipStream_t s);
 hipError_t launch_sum_cells(const double *g, int64_t n, int R, double *out, hipStream_t s);
 int adjoint_capacity(int np, int R, int device);
+
+// operator-split driver support (transport.hip)
+hipError_t launch_transport2d(int nx, int ny, int ncomp, const double *in, int64_t ld, const double *u,
+                              const double *dt, double dx, double D, const double *inflow, double *out,
+                              hipStream_t s);
 int adjoint_slot_checkpoints();
 size_t lds_bytes_for(int np);
 
