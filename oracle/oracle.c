@@ -34,6 +34,10 @@
 #define OM_MAXSP 256
 #define OM_MAXN (OM_MAXSP + 1)
 
+/* reactor mode bits of the "mode" arguments below */
+#define OM_ISOTHERMAL 1 /* T held fixed (f_T = 0) */
+#define OM_CONSTV 2     /* constant volume: the p argument is the density */
+
 enum { RX_PLAIN = 0, RX_THIRD = 1, RX_TROE = 2 };
 
 typedef struct {
@@ -226,24 +230,24 @@ void om_thermo(const omech *m, double T, double *cp_R, double *h_RT, double *s_R
     for (int k = 0; k < m->N; ++k) thermo_d(m, k, T, &cp_R[k], &h_RT[k], &s_R[k]);
 }
 
-/* y = (Y_0..Y_{N-1}, T).  aux: rho, cp, sum h wdot, Wbar. */
+/* y = (Y_0..Y_{N-1}, T).  aux: rho, cp, sum h wdot, Wbar.  constv: p is rho. */
 void om_rates(const omech *m, double p, const double *y, const double *dlnA, double *kf, double *kr,
-              double *q, double *wdot, double *aux)
+              double *q, double *wdot, double *aux, int constv)
 {
-    rates_d(m, p, y, dlnA, kf, kr, q, wdot, aux);
+    rates_d(m, p, y, dlnA, kf, kr, q, wdot, aux, constv);
 }
 
-void om_rhs(const omech *m, double p, const double *y, const double *dlnA, double *f, int isothermal)
+void om_rhs(const omech *m, double p, const double *y, const double *dlnA, double *f, int mode)
 {
-    rhs_d(m, p, y, dlnA, f, isothermal);
+    rhs_d(m, p, y, dlnA, f, mode);
 }
 
 /* dense Jacobians, row-major J[i*(N+1)+j] = d f_i / d y_j */
-void om_jac_fd(const omech *m, double p, const double *y, const double *dlnA, double *J, int isothermal)
+void om_jac_fd(const omech *m, double p, const double *y, const double *dlnA, double *J, int mode)
 {
     const int n = m->N + 1;
     double f0[OM_MAXN], f1[OM_MAXN], yp[OM_MAXN];
-    rhs_d(m, p, y, dlnA, f0, isothermal);
+    rhs_d(m, p, y, dlnA, f0, mode);
     const double seps = sqrt(2.220446049250313e-16);
     for (int j = 0; j < n; ++j) {
         memcpy(yp, y, sizeof(double) * n);
@@ -251,14 +255,14 @@ void om_jac_fd(const omech *m, double p, const double *y, const double *dlnA, do
         double d = seps * fmax(fabs(y[j]), typ);
         yp[j] = y[j] + d;
         d = yp[j] - y[j];
-        rhs_d(m, p, yp, dlnA, f1, isothermal);
+        rhs_d(m, p, yp, dlnA, f1, mode);
         for (int i = 0; i < n; ++i) J[i * n + j] = (f1[i] - f0[i]) / d;
     }
 }
 
 static const double CS_H = 1e-30;
 
-void om_jac_cs(const omech *m, double p, const double *y, const double *dlnA, double *J, int isothermal)
+void om_jac_cs(const omech *m, double p, const double *y, const double *dlnA, double *J, int mode)
 {
     const int n = m->N + 1;
     double complex yz[OM_MAXN], fz[OM_MAXN], dz[OM_MAXSP * 8];
@@ -271,7 +275,7 @@ void om_jac_cs(const omech *m, double p, const double *y, const double *dlnA, do
     for (int j = 0; j < n; ++j) {
         for (int i = 0; i < n; ++i) yz[i] = y[i];
         yz[j] += I * CS_H;
-        rhs_z(m, p, yz, dl, fz, isothermal);
+        rhs_z(m, p, yz, dl, fz, mode);
         for (int i = 0; i < n; ++i) J[i * n + j] = cimag(fz[i]) / CS_H;
     }
     if (dl && dl != dz) free(dl);
@@ -382,7 +386,7 @@ typedef struct {
     const omech *m;
     double p;
     const double *dlnA;
-    int isothermal;
+    int mode;
     int ns;             /* number of sensitivity directions */
     const double *dpar; /* [ns][R] parameter directions (NULL: none) */
 } sysdef;
@@ -391,7 +395,7 @@ static void sys_rhs(const sysdef *sd, const double *z, double *fz)
 {
     const omech *m = sd->m;
     const int n = m->N + 1, R = m->R_;
-    rhs_d(m, sd->p, z, sd->dlnA, fz, sd->isothermal);
+    rhs_d(m, sd->p, z, sd->dlnA, fz, sd->mode);
     if (sd->ns == 0) return;
     double complex yz[OM_MAXN], out[OM_MAXN];
     double complex *dl = malloc(sizeof(double complex) * R);
@@ -400,7 +404,7 @@ static void sys_rhs(const sysdef *sd, const double *z, double *fz)
         for (int i = 0; i < n; ++i) yz[i] = z[i] + I * CS_H * sv[i];
         for (int j = 0; j < R; ++j)
             dl[j] = (sd->dlnA ? sd->dlnA[j] : 0.0) + (sd->dpar ? I * CS_H * sd->dpar[s * R + j] : 0.0);
-        rhs_z(m, sd->p, yz, dl, out, sd->isothermal);
+        rhs_z(m, sd->p, yz, dl, out, sd->mode);
         for (int i = 0; i < n; ++i) fz[n * (1 + s) + i] = cimag(out[i]) / CS_H;
     }
     free(dl);
@@ -514,12 +518,12 @@ static int radau_integrate(const sysdef *sd, double *z, double dt, double rtol, 
         if (h < 1e-20 * dt) { status = CELL_H_UNDERFLOW; break; }
         int final = 0;
         if (t + h >= dt) { h = dt - t; final = 1; }
-        om_jac_fd(m, sd->p, z, sd->dlnA, w.J, sd->isothermal);
+        om_jac_fd(m, sd->p, z, sd->dlnA, w.J, sd->mode);
         for (int i = 0; i < nz; ++i) sc[i] = atol + rtol * fabs(z[i]);
         int fail = radau_step(sd, &w, z, h, sc, zh);
         if (!fail) fail = radau_step(sd, &w, z, 0.5 * h, sc, zm);
         if (!fail) {
-            om_jac_fd(m, sd->p, zm, sd->dlnA, w.J, sd->isothermal);
+            om_jac_fd(m, sd->p, zm, sd->dlnA, w.J, sd->mode);
             fail = radau_step(sd, &w, zm, 0.5 * h, sc, z2);
         }
         if (fail) {
@@ -566,7 +570,7 @@ done:
  * alias T0/Y0.  dlnA: [R] or NULL.  Returns the number of failed cells. */
 int om_integrate(const omech *m, int ncells, const double *T0, const double *p, const double *Y0,
                  const double *dt, const double *dlnA, double rtol, double atol, int max_steps,
-                 double *T1, double *Y1, int *nacc, int *nrej, int *status, int nthreads, int isothermal)
+                 double *T1, double *Y1, int *nacc, int *nrej, int *status, int nthreads, int mode)
 {
     const int N = m->N;
     int nfail = 0;
@@ -584,7 +588,7 @@ int om_integrate(const omech *m, int ncells, const double *T0, const double *p, 
         if (!ok) {
             st = CELL_BAD_INPUT;
         } else {
-            sysdef sd = {m, p[c], dlnA, isothermal, 0, NULL};
+            sysdef sd = {m, p[c], dlnA, mode, 0, NULL};
             st = radau_integrate(&sd, z, dt[c], rtol, atol, max_steps, &na, &nr);
         }
         for (int k = 0; k < N; ++k) Y1[(size_t)c * N + k] = z[k];

@@ -36,6 +36,11 @@ _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 
 
+def _mode(isothermal, constv):
+    """Reactor mode bits of the C functions (isothermal 1, constant volume 2)."""
+    return (1 if isothermal else 0) | (2 if constv else 0)
+
+
 def _opt_dp(x):
     return None if x is None else np.ascontiguousarray(x, np.float64).ctypes.data_as(C.POINTER(C.c_double))
 
@@ -51,7 +56,7 @@ def lib():
         L.om_n_species.argtypes = [C.c_void_p]
         L.om_n_reactions.argtypes = [C.c_void_p]
         L.om_thermo.argtypes = [C.c_void_p, C.c_double, _dp, _dp, _dp]
-        L.om_rates.argtypes = [C.c_void_p, C.c_double, _dp, C.c_void_p, _dp, _dp, _dp, _dp, _dp]
+        L.om_rates.argtypes = [C.c_void_p, C.c_double, _dp, C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.c_int]
         L.om_rhs.argtypes = [C.c_void_p, C.c_double, _dp, C.c_void_p, _dp, C.c_int]
         L.om_jac_fd.argtypes = [C.c_void_p, C.c_double, _dp, C.c_void_p, _dp, C.c_int]
         L.om_jac_cs.argtypes = [C.c_void_p, C.c_double, _dp, C.c_void_p, _dp, C.c_int]
@@ -91,30 +96,31 @@ class Oracle:
         lib().om_thermo(self.h, float(T), cp, h, s)
         return cp, h, s
 
-    def rates(self, T, p, Y, dlnA=None):
-        """Returns kf, kr, q [R], wdot [N] (mol/m^3/s) and aux (rho, cp, sum h wdot, Wbar)."""
+    def rates(self, T, p, Y, dlnA=None, constv=False):
+        """Returns kf, kr, q [R], wdot [N] (mol/m^3/s) and aux (rho, cp, sum h wdot, Wbar).
+        constv: p is the density of a constant-volume reactor."""
         y = np.ascontiguousarray(np.append(np.asarray(Y, np.float64), T))
         kf, kr, q = (np.empty(self.R) for _ in range(3))
         wdot, aux = np.empty(self.N), np.empty(4)
-        lib().om_rates(self.h, float(p), y, _opt_dp(dlnA), kf, kr, q, wdot, aux)
+        lib().om_rates(self.h, float(p), y, _opt_dp(dlnA), kf, kr, q, wdot, aux, int(constv))
         return kf, kr, q, wdot, aux
 
-    def rhs(self, y, p, dlnA=None, isothermal=False):
+    def rhs(self, y, p, dlnA=None, isothermal=False, constv=False):
         y = np.ascontiguousarray(y, np.float64)
         f = np.empty(self.N + 1)
-        lib().om_rhs(self.h, float(p), y, _opt_dp(dlnA), f, int(isothermal))
+        lib().om_rhs(self.h, float(p), y, _opt_dp(dlnA), f, _mode(isothermal, constv))
         return f
 
-    def jac_fd(self, y, p, dlnA=None, isothermal=False):
+    def jac_fd(self, y, p, dlnA=None, isothermal=False, constv=False):
         y = np.ascontiguousarray(y, np.float64)
         J = np.empty((self.N + 1, self.N + 1))
-        lib().om_jac_fd(self.h, float(p), y, _opt_dp(dlnA), J, int(isothermal))
+        lib().om_jac_fd(self.h, float(p), y, _opt_dp(dlnA), J, _mode(isothermal, constv))
         return J
 
-    def jac_cs(self, y, p, dlnA=None, isothermal=False):
+    def jac_cs(self, y, p, dlnA=None, isothermal=False, constv=False):
         y = np.ascontiguousarray(y, np.float64)
         J = np.empty((self.N + 1, self.N + 1))
-        lib().om_jac_cs(self.h, float(p), y, _opt_dp(dlnA), J, int(isothermal))
+        lib().om_jac_cs(self.h, float(p), y, _opt_dp(dlnA), J, _mode(isothermal, constv))
         return J
 
     def dfdp_cs(self, y, p, dlnA=None):
@@ -125,7 +131,9 @@ class Oracle:
 
     # -- integration ---------------------------------------------------------
     def integrate(self, T0, p, Y0, dt, dlnA=None, rtol=1e-6, atol=1e-12, max_steps=100000,
-                  nthreads=0, isothermal=False):
+                  nthreads=0, isothermal=False, constv=False):
+        """Integrate cells over dt[c]; p is the pressure, or with constv the
+        density of a constant-volume reactor (rho fixed, p varies)."""
         T0 = np.ascontiguousarray(T0, np.float64)
         n = T0.shape[0]
         p = np.ascontiguousarray(np.broadcast_to(p, (n,)), np.float64)
@@ -134,7 +142,7 @@ class Oracle:
         T1, Y1 = np.empty(n), np.empty((n, self.N))
         nacc, nrej, st = (np.zeros(n, np.int32) for _ in range(3))
         lib().om_integrate(self.h, n, T0, p, Y0, dt, _opt_dp(dlnA), rtol, atol, max_steps, T1, Y1,
-                           nacc, nrej, st, int(nthreads), int(isothermal))
+                           nacc, nrej, st, int(nthreads), _mode(isothermal, constv))
         return dict(T=T1, Y=Y1, n_acc=nacc, n_rej=nrej, status=st)
 
     def integrate_sens(self, T0, p, Y0, dt, s0, dpar=None, dlnA=None, rtol=1e-10, atol=1e-16,

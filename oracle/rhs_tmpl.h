@@ -19,6 +19,10 @@
  *   q    = kf prod C^nu' - kr prod C^nu''   (times [M] for third-body)
  *   dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum_k h_k wdot_k / (rho cp)
  * with rho = p Wbar/(R T), C_k = rho Y_k/W_k.
+ * The constant-volume variant (adiabatic, rigid vessel) holds rho fixed
+ * instead of p (the argument p then carries rho), so C_k = rho Y_k/W_k with
+ * that rho, and the energy balance is on internal energy:
+ *   dT/dt = -sum_k u_k wdot_k / (rho cv),  u_k = h_k - R T,  cv = cp - R/Wbar.
  *
  * Expects: SC, FN(name) (function-name decoration), SEXP, SLOG, SPOW.
  */
@@ -33,12 +37,13 @@ static void FN(thermo)(const omech *m, int k, SC T, SC *cp_R, SC *h_RT, SC *s_R)
     *s_R = a[0] * SLOG(T) + a[1] * T + a[2] * T2 / 2.0 + a[3] * T3 / 3.0 + a[4] * T4 / 4.0 + a[6];
 }
 
-/* Rates of progress and production rates.  y = (Y_0..Y_{N-1}, T);
+/* Rates of progress and production rates.  y = (Y_0..Y_{N-1}, T); p is the
+ * pressure, or with constv != 0 the density rho;
  * dlnA[j] (may be NULL) multiplies reaction j's net rate by exp(dlnA[j]).
  * Outputs (any may be NULL): kf[R], kr[R], q[R], wdot[N] (mol/m^3/s),
  * and through aux[4]: rho, cp (J/kg/K), sum_k h_k wdot_k, Wbar. */
 static void FN(rates)(const omech *m, double p, const SC *y, const SC *dlnA, SC *kf_out,
-                      SC *kr_out, SC *q_out, SC *wdot, SC *aux)
+                      SC *kr_out, SC *q_out, SC *wdot, SC *aux, int constv)
 {
     const int N = m->N;
     const double R = m->R;
@@ -50,7 +55,7 @@ static void FN(rates)(const omech *m, double p, const SC *y, const SC *dlnA, SC 
         sumYW += y[k] / m->W[k];
     }
     SC Wbar = 1.0 / sumYW;
-    SC rho = p * Wbar / (R * T);
+    SC rho = constv ? (SC)p : p * Wbar / (R * T);
     SC cp = 0.0;
     for (int k = 0; k < N; ++k) {
         C[k] = rho * y[k] / m->W[k];
@@ -127,13 +132,25 @@ static void FN(rates)(const omech *m, double p, const SC *y, const SC *dlnA, SC 
     }
 }
 
-/* f(y): dY_k/dt for k < N and dT/dt in f[N]; with isothermal != 0, f[N] = 0. */
-static void FN(rhs)(const omech *m, double p, const SC *y, const SC *dlnA, SC *f, int isothermal)
+/* f(y): dY_k/dt for k < N and dT/dt in f[N].  mode bits: OM_ISOTHERMAL
+ * (f[N] = 0), OM_CONSTV (constant-volume reactor; p carries the density). */
+static void FN(rhs)(const omech *m, double p, const SC *y, const SC *dlnA, SC *f, int mode)
 {
     const int N = m->N;
+    const int constv = (mode & OM_CONSTV) != 0;
     SC wdot[OM_MAXSP], aux[4];
-    FN(rates)(m, p, y, dlnA, NULL, NULL, NULL, wdot, aux);
-    SC rho = aux[0], cp = aux[1], hw = aux[2];
+    FN(rates)(m, p, y, dlnA, NULL, NULL, NULL, wdot, aux, constv);
+    SC rho = aux[0], cp = aux[1], hw = aux[2], Wbar = aux[3];
     for (int k = 0; k < N; ++k) f[k] = m->W[k] * wdot[k] / rho;
-    f[N] = isothermal ? (SC)0.0 : -hw / (rho * cp);
+    if (mode & OM_ISOTHERMAL) {
+        f[N] = 0.0;
+    } else if (constv) {
+        SC sw = 0.0;
+        for (int k = 0; k < N; ++k) sw += wdot[k];
+        SC uw = hw - m->R * y[N] * sw;       /* sum_k (h_k - R T) wdot_k */
+        SC cv = cp - m->R / Wbar;
+        f[N] = -uw / (rho * cv);
+    } else {
+        f[N] = -hw / (rho * cp);
+    }
 }
