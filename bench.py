@@ -30,9 +30,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cells, budget_s=15.0):
+def cpu_baseline(cells, budget_s=15.0, constv=False):
     """The oracle (plain dense Radau IIA, FD Jacobian) at the production
-    tolerance on a stratified sample of the same batch, all host threads."""
+    tolerance on a stratified sample of the same batch, all host threads.
+    constv: the cells' "p" entries are densities of constant-volume reactors."""
     from oracle.oracle import Oracle, max_threads
     from synth.cells import stratified
     o = Oracle(cells["mech"].to_text())
@@ -43,14 +44,14 @@ def cpu_baseline(cells, budget_s=15.0):
     sample = rng.permutation(sample)
     # warm-up on a few cells, then time batches until the budget is used
     o.integrate(cells["T"][sample[:4]], cells["p"][sample[:4]], cells["Y"][sample[:4]], cells["dt"][sample[:4]],
-                rtol=1e-6, atol=1e-12, nthreads=threads)
+                rtol=1e-6, atol=1e-12, nthreads=threads, constv=constv)
     pos = 0
     while t_used < budget_s and pos < sample.size:
         idx = sample[pos:pos + per * threads]
         pos += idx.size
         t0 = time.perf_counter()
         r = o.integrate(cells["T"][idx], cells["p"][idx], cells["Y"][idx], cells["dt"][idx], rtol=1e-6, atol=1e-12,
-                        nthreads=threads)
+                        nthreads=threads, constv=constv)
         t_used += time.perf_counter() - t0
         done += idx.size
         assert np.all(r["status"] == 0)
@@ -74,8 +75,9 @@ def main():
     ap.add_argument("--spinup", type=int, default=400,
                     help="lts workload: untimed split steps before the warm-up and the timed steps")
     ap.add_argument("--no-gradient", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "lts", "copy"],
-                    help="c2: the headline (default); c3: the uneven batch, queue vs static mapping; "
+    ap.add_argument("--workload", default="c2", choices=["c2", "c2v", "c3", "c5", "lts", "copy"],
+                    help="c2: the headline (default); c2v: the same cells as constant-volume reactors; "
+                         "c3: the uneven batch, queue vs static mapping; "
                          "c5: 20 chained substeps, forward and gradient; lts: split steps (chemistry + "
                          "transport) of the 170 x 170 flame field with local time steps; copy: a plain "
                          "device copy of known size (calibrates the HBM byte counters)")
@@ -100,6 +102,12 @@ def main():
         return bench_lts(args)
     log("bench: generating C2 workload")
     cells = make_cells("C2")
+    constv = args.workload == "c2v"
+    if constv:
+        # rigid vessels at each cell's initial density; the "p" input is rho
+        W = cells["mech"].molar_masses()
+        cells["p"] = cells["p"] * (1.0 / (cells["Y"] / W).sum(1)) / (8.314462618 * cells["T"])
+        args.no_gradient = True
     n = args.cells
     idx = np.arange(n) % cells["T"].size
     dev = "cuda:0"
@@ -113,11 +121,13 @@ def main():
         log("bench: autotuning the launch configuration on a 16,384-cell sample")
         s_ = torch.tensor(np.random.default_rng(0).choice(n, 16384, replace=False), device=dev)
         launch, tune_ms = autotune.tune(mech, T[s_].contiguous(), p[s_].contiguous(), Y[:, s_].contiguous(),
-                                        dt[s_].contiguous(), use_cache=False, reps=1)
+                                        dt[s_].contiguous(), use_cache=False, reps=1,
+                                        reactor="const_v" if constv else "const_p")
     else:
         launch = dict(mode=args.mode, tile=args.tile, grid=0, order=args.order)
         tune_ms = None
-    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, **launch)
+    reactor = "const_v" if constv else "const_p"
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, **launch)
     stream = torch.cuda.current_stream()
     out = None
     log(f"bench: warmup {args.warmup}")
@@ -148,25 +158,27 @@ def main():
     kern_s = float(np.mean(launch_ms)) / 1e3
     achieved = flops / kern_s / 1e12
     res = {
-        "metric": "cells/s integrated @rtol 1e-6, 53-species mech; gradient/forward time ratio",
+        "metric": "cells/s integrated @rtol 1e-6, 53-species mech" + (
+            ", constant-volume reactor" if constv else "; gradient/forward time ratio"),
         "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "C2: 65,536 reactor cells, seeded 53-species/325-reaction C/H/O/N "
                                "mechanism (30 third-body, 15 Troe), 1-10 atm, T0 300-2400 K in thirds "
-                               "(unburnt/near-ignition/equilibrated), dt 1e-4 s, rtol 1e-6, atol 1e-12",
+                               "(unburnt/near-ignition/equilibrated), dt 1e-4 s, rtol 1e-6, atol 1e-12" + (
+                                   "; constant-volume reactors at each cell's initial density" if constv else ""),
                    "cells": n, "launch": launch, "autotune_sample_ms": tune_ms,
                    "kernel": "k_integrate<56>" if launch["mode"] == "plain" else f"k_integrate_{launch['mode']}<56>",
                    "steps_per_cell_mean": float((nacc + nrej).mean()),
                    "accepted_mean": float(nacc.mean()), "rejected_mean": float(nrej.mean()),
                    "gradient_forward_ratio": None},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(launch),
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None if constv else measured_traffic(launch),
                      "kernel_ms": kern_s * 1e3, "flops_per_launch": flops},
     }
     if launch["mode"] != "plain":
         # the same batch through the plain one-workgroup-per-cell launch, for comparison
-        pp = sc.Plan(mech, rtol=1e-6, atol=1e-12, mode="plain")
+        pp = sc.Plan(mech, rtol=1e-6, atol=1e-12, mode="plain", reactor=reactor)
         o2 = pp.integrate(T, p, Y, dt)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -183,7 +195,7 @@ def main():
         res["gradient"] = grad
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
-        res["cpu_baseline"] = cpu_baseline(cells)
+        res["cpu_baseline"] = cpu_baseline(cells, constv=constv)
     print(json.dumps(res), flush=True)
 
 

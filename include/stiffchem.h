@@ -69,6 +69,19 @@ enum {
 typedef struct sc_mech sc_mech; /* immutable after load; shareable across threads */
 typedef struct sc_plan sc_plan; /* a mechanism on one device; one stream at a time */
 
+/* Reactor model of every cell (both adiabatic, ideal gas).  Constant
+ * pressure: the per-cell array p of the calls below is the pressure [Pa],
+ * energy balance on enthalpy.  Constant volume (a rigid vessel): that array
+ * is the density rho [kg/m^3], held fixed while the pressure follows
+ * p = rho R T / Wbar; energy balance on internal energy,
+ *   dT/dt = -sum_k (h_k - R T) wdot_k / (rho cv),  cv = cp - R / Wbar,
+ * and C_k = rho Y_k / W_k.  sc_vjp and sc_adjoint support constant
+ * pressure only (SC_EUNSUPPORTED otherwise). */
+typedef enum {
+    SC_REACTOR_CONST_P = 0,
+    SC_REACTOR_CONST_V = 1
+} sc_reactor;
+
 typedef struct {
     double rtol;        /* relative tolerance (default 1e-6) */
     double atol;        /* absolute tolerance, every component (default 1e-12) */
@@ -85,6 +98,7 @@ typedef struct {
                            cap).  Error control sees only the state; a cap makes the
                            steps also resolve how perturbations relax, which the
                            adjoint's gradients then follow (see sc_adjoint) */
+    int32_t reactor;    /* SC_REACTOR_CONST_P (default) or SC_REACTOR_CONST_V */
 } sc_options;
 
 typedef struct {

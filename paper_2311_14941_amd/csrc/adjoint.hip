@@ -342,7 +342,7 @@ __device__ void adjoint_cell(const DevMech &m, const Opts &o, double *lds, int64
 }
 
 template <int NP>
-__global__ void __launch_bounds__(WAVE) k_adjoint(DevMech m, Opts o, int64_t n, const double *T0, const double *P,
+__global__ void __launch_bounds__(WAVE) k_adjoint(DevMech mk, Opts o, int64_t n, const double *T0, const double *P,
                                                   const double *Y0, int64_t ld, const double *DT,
                                                   const double *dlnA, const double *h_in, const double *gT1,
                                                   const double *gY1, double *gT0, double *gY0, double *gcell,
@@ -351,6 +351,7 @@ __global__ void __launch_bounds__(WAVE) k_adjoint(DevMech m, Opts o, int64_t n, 
                                                   unsigned long long *queue, const int32_t *perm)
 {
     extern __shared__ double lds[];
+    const DevMech m = fix_reactor<false>(mk);  // constant pressure only
     const int lane = threadIdx.x;
     double *slot = scratch + (int64_t)blockIdx.x * slot_doubles;
 #pragma unroll 1
@@ -367,11 +368,12 @@ __global__ void __launch_bounds__(WAVE) k_adjoint(DevMech m, Opts o, int64_t n, 
 
 // Vector-Jacobian product of the right-hand side at n states.
 template <int NP>
-__global__ void __launch_bounds__(WAVE) k_vjp(DevMech m, int64_t n, const double *T, const double *P,
+__global__ void __launch_bounds__(WAVE) k_vjp(DevMech mk, int64_t n, const double *T, const double *P,
                                               const double *Y, int64_t ld, const double *dlnA, const double *wT,
                                               const double *wY, double *gT, double *gY, double *gcell)
 {
     extern __shared__ double lds[];
+    const DevMech m = fix_reactor<false>(mk);  // constant pressure only
     const int lane = threadIdx.x;
     const int64_t c = blockIdx.x;
     if (c >= n) return;

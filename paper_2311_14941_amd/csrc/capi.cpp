@@ -137,6 +137,7 @@ void sc_default_options(sc_options *opt)
     opt->tile = 1;
     opt->grid = 0;
     opt->order = 0;
+    opt->reactor = SC_REACTOR_CONST_P;
 }
 
 sc_status sc_mech_load(const char *text, size_t len, sc_mech **out)
@@ -216,6 +217,7 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
     if (o.grid < 0) return fail(SC_EINVAL, "grid must be >= 0");
     if (o.fixed_step != 0 && o.fixed_step != 1) return fail(SC_EINVAL, "fixed_step must be 0 or 1");
     if (!(o.hmax_frac >= 0.0) || !std::isfinite(o.hmax_frac)) return fail(SC_EINVAL, "hmax_frac must be >= 0");
+    if (o.reactor != SC_REACTOR_CONST_P && o.reactor != SC_REACTOR_CONST_V) return fail(SC_EINVAL, "unknown reactor");
     DeviceGuard g(device);
     if (!g.ok) return fail(SC_EHIP, "hipSetDevice failed");
     sc_plan *p = nullptr;
@@ -234,6 +236,7 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
     d.N = t.N;
     d.R = t.R;
     d.nt = t.n_troe;
+    d.cv = o.reactor == SC_REACTOR_CONST_V ? 1 : 0;
     d.Rgas = t.Rgas;
     d.lnp0R = std::log(t.p0 / t.Rgas);
     // species table, reaction records, Troe records
@@ -389,7 +392,9 @@ sc_status sc_vjp(sc_plan *plan, int64_t n, const double *T, const double *p, con
                  double *g_dlnA_cell, void *stream)
 {
     sc_status s = check_common(plan, n, ld, {T, p, Y, wT, wY, gT, gY});
-    if (s != SC_OK || n == 0) return s;
+    if (s != SC_OK) return s;
+    if (plan->dm.cv) return fail(SC_EUNSUPPORTED, "the VJP supports the constant-pressure reactor only");
+    if (n == 0) return SC_OK;
     DeviceGuard g(plan->device);
     hipError_t e = scdev::launch_vjp(plan->np, plan->dm, n, T, p, Y, ld, dlnA, wT, wY, gT, gY, g_dlnA_cell,
                                      (hipStream_t)stream);
@@ -415,6 +420,7 @@ sc_status sc_adjoint(sc_plan *plan, int64_t n, const double *T0, const double *p
     if (peak_bytes) *peak_bytes = 0;
     sc_status s = check_common(plan, n, ld, {T0, p, Y0, dt, gT1, gY1, gT0, gY0, cell_status});
     if (s != SC_OK) return s;
+    if (plan->dm.cv) return fail(SC_EUNSUPPORTED, "the adjoint supports the constant-pressure reactor only");
     const int R = plan->dm.R;
     hipStream_t st = (hipStream_t)stream;
     DeviceGuard g(plan->device);

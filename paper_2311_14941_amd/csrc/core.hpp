@@ -134,6 +134,8 @@ __device__ __forceinline__ Dual wave_sum(Dual v) { return {wave_sum(v.v), wave_s
 // the part a pass reports: the value (S = double) or the derivative (Dual)
 __device__ __forceinline__ double part(double x) { return x; }
 __device__ __forceinline__ double part(Dual x) { return x.d; }
+__device__ __forceinline__ double value(double x) { return x; }
+__device__ __forceinline__ double value(Dual x) { return x.v; }
 
 // LDS access of a scalar: a Dual's derivative lives toff doubles from its value
 template <class S>
@@ -161,6 +163,16 @@ __device__ __forceinline__ void lds_add(double *lds, int i, Dual x, int toff)
     atomicAdd(&lds[i + toff], x.d);
 }
 
+// The reactor model as a compile-time constant.  Every device routine is
+// inlined into its kernel, so a kernel that calls this on its DevMech
+// argument gets the branches on m.cv folded away.
+template <bool CV>
+__device__ __forceinline__ DevMech fix_reactor(DevMech m)
+{
+    m.cv = CV ? 1 : 0;
+    return m;
+}
+
 // ---------------------------------------------------------------------------
 // LDS layout of one cell (doubles)
 // ---------------------------------------------------------------------------
@@ -181,6 +193,8 @@ struct Lds {
 };
 
 // Per-cell uniform quantities at the point where a right-hand side was taken.
+// p is the pressure; cp the heat capacity of the reactor's energy balance
+// (c_p at constant pressure, c_v at constant volume).
 template <class S = double>
 struct Mix {
     S T, invT, lnT;
@@ -211,7 +225,8 @@ __device__ __forceinline__ Thermo<S> nasa7(const DevMech &m, int k, S T, S lnT, 
 
 // Mixture state from the lane-distributed y (lane k < N: Y_k, lane N: T);
 // writes C, g/RT, h/RT to LDS and clears the accumulators.  With S = Dual
-// the derivatives go toff doubles beyond the values.
+// the derivatives go toff doubles beyond the values.  p is the pressure, or
+// in a constant-volume reactor the density.
 template <int NP, class S = double>
 __device__ __forceinline__ Mix<S> mixture(const DevMech &m, double *lds, S y, double p, Thermo<S> &th, int lane,
                                           int toff = 0)
@@ -230,8 +245,14 @@ __device__ __forceinline__ Mix<S> mixture(const DevMech &m, double *lds, S y, do
         cpw = th.cpR * yw;
     }
     x.Wbar = 1.0 / wave_sum(yw);
-    x.rho = p * x.Wbar * x.invT / m.Rgas;
     x.cp = m.Rgas * wave_sum(cpw);
+    if (m.cv) {
+        x.rho = p;
+        x.p = value(p * m.Rgas * x.T / x.Wbar);
+        x.cp = x.cp - m.Rgas / x.Wbar;
+    } else {
+        x.rho = p * x.Wbar * x.invT / m.Rgas;
+    }
     if (lane < N) {
         lds_put(lds, Lds<NP>::C + lane, x.rho * yw, toff);
         lds_put(lds, Lds<NP>::G + lane, th.hRT - th.sR, toff);
@@ -239,6 +260,7 @@ __device__ __forceinline__ Mix<S> mixture(const DevMech &m, double *lds, S y, do
         lds_put(lds, Lds<NP>::WD + lane, S(0.0), toff);
         lds[Lds<NP>::UA + lane] = 0.0;
     }
+    if (m.cv && lane == N) lds[Lds<NP>::UA + N] = 0.0;  // temperature-row accumulator (constant volume)
     return x;
 }
 
@@ -306,7 +328,9 @@ __device__ __forceinline__ RxOut<S> reaction(const DevMech &m, const double *lds
     const int dnu = rr.dnu;
     const S lnKc = -dG + dnu * (m.lnp0R - x.lnT);
     // third-body concentration, rewritten with sum_k C_k = p/(R T):
-    // [M] = p/(RT) + sum_enhanced (alpha - 1) C
+    // [M] = p/(RT) + sum_enhanced (alpha - 1) C.  At constant pressure p/(RT)
+    // depends on T alone; at constant volume it is rho/Wbar, a function of
+    // every C_k (dM/dC_k = 1, the rank-one part the caller adds)
     S M = 0.0;
     const int ne = rr.neff;
     S ec[sc::MAXENH];
@@ -364,7 +388,7 @@ __device__ __forceinline__ RxOut<S> reaction(const DevMech &m, const double *lds
     o.d[5] = np > 2 ? -fsc * kr * dipow(pc[2], pn[2]) * s0 * s1 : S(0.0);
     const S dlnkinf = (rr.b + rr.EaR * x.invT) * x.invT;
     const S dlnKc = (dH - dnu) * x.invT;
-    const S dMdT = -x.p * x.invT * x.invT / m.Rgas;
+    const S dMdT = m.cv ? S(0.0) : -x.p * x.invT * x.invT / m.Rgas;
     S dqM = 0.0;  // dq/d[M]
     S dlnkf = dlnkinf;
     if (kind == sc::RX_THIRD) {
@@ -384,7 +408,9 @@ __device__ __forceinline__ RxOut<S> reaction(const DevMech &m, const double *lds
         eu -= (i < nr ? rc[i] : S(0.0)) * o.d[i] + (i < np ? pc[i] : S(0.0)) * o.d[3 + i];
 #pragma unroll
     for (int e = 0; e < sc::MAXENH; ++e) eu -= ec[e] * o.d[6 + e];
-    o.euler = eu;
+    // constant pressure: the Euler remainder; constant volume: dq/d[M], the
+    // weight of the rank-one part of dq/dC
+    o.euler = m.cv ? dqM : eu;
     o.dH = dH;
     return o;
 }
@@ -440,6 +466,7 @@ __device__ __forceinline__ void scatter(const DevMech &m, double *lds, const RxR
         for (int s = 0; s < sc::NDEP; ++s)
             if (use[s]) atomicAdd(&P[N * Lds<NP>::PS + col[s]], dHJ * o.d[s]);
         atomicAdd(&P[N * Lds<NP>::PS + N], dHJ * o.dT);
+        if (m.cv) atomicAdd(&lds[Lds<NP>::UA + N], dHJ * o.euler);
     }
 }
 
@@ -463,7 +490,7 @@ __device__ double rhs(const DevMech &m, double *lds, double y, double p, const d
     if (lane < N) {
         const double wd = lds[Lds<NP>::WD + lane];
         f = m.W()[lane] * wd / x.rho;
-        hw = th.hRT * wd;
+        hw = (m.cv ? th.hRT - 1.0 : th.hRT) * wd;  // h_k/RT, or u_k/RT at constant volume
     }
     const double H = m.Rgas * x.T * wave_sum(hw);
     if (lane == N) f = -H / (x.rho * x.cp);
@@ -497,39 +524,52 @@ __device__ double rhs_jac(const DevMech &m, double *lds, double y, double p, con
         const RxRec rr = load_rec(m, j);
         const double dl = dlnA ? dlnA[rr.orig] : 0.0;
         const RxOut<> o = reaction<true>(m, lds, rr, x, dl, Lds<NP>::C, Lds<NP>::G, Lds<NP>::H);
-        scatter<NP, true>(m, lds, rr, o, o.dH * RT);
+        // temperature-row weight: the reaction's enthalpy, or at constant
+        // volume its internal energy (dH - dnu) R T
+        scatter<NP, true>(m, lds, rr, o, m.cv ? (o.dH - rr.dnu) * RT : o.dH * RT);
     }
     wave_sync();
-    double f = 0.0, hw = 0.0, eu = 0.0, cpf = 0.0, dcp = 0.0, uk = 0.0, Wk = 0.0;
+    // m.cv: the energy balance is on u_k = h_k - R T, the heat capacity c_v
+    const double one = m.cv ? 1.0 : 0.0;
+    double f = 0.0, hw = 0.0, eu = 0.0, cpf = 0.0, dcp = 0.0, uk = 0.0, ua = 0.0, Wk = 0.0;
     if (lane < N) {
         Wk = m.W()[lane];
         const double iw = m.invW()[lane];
         const double wd = lds[Lds<NP>::WD + lane];
+        ua = lds[Lds<NP>::UA + lane];
         f = Wk * wd / x.rho;
-        uk = Wk * lds[Lds<NP>::UA + lane] / x.rho;
-        hw = th.hRT * wd;
-        eu = th.hRT * uk * iw;   // (h_k/(R T W_k)) u_k
-        cpf = th.cpR * f * iw;   // cp_k/(R W_k) f_k
-        dcp = th.dcpR * y * iw;  // dcp_k/dT/(R W_k) Y_k
+        uk = Wk * ua / x.rho;
+        hw = (th.hRT - one) * wd;
+        eu = th.hRT * uk * iw;           // (h_k/(R T W_k)) u_k
+        cpf = (th.cpR - one) * f * iw;   // cp_k/(R W_k) f_k (cv_k at constant volume)
+        dcp = th.dcpR * y * iw;          // dcp_k/dT/(R W_k) Y_k
     }
     const double H = RT * wave_sum(hw);
-    const double Eu = RT * wave_sum(eu);  // sum_k (h_k/W_k) u_k
+    const double Eu = m.cv ? 0.0 : RT * wave_sum(eu);  // sum_k (h_k/W_k) u_k
     const double Scpf = m.Rgas * wave_sum(cpf);
     const double Sdcp = m.Rgas * wave_sum(dcp);
     const double fT = -H / (x.rho * x.cp);
     if (lane == N) f = fT;
-    // fold the column-dependent parts of the temperature row into P[N][*]:
-    // J_Tm = -(1/cp) (1/W_m) (P_Tm + Wbar Eu + fT cp_m),
-    // J_TT = -(1/cp) (P_TT/rho + Eu/T + sum cp_k f_k/W_k + fT sum dcp_k Y_k/W_k)
+    // fold the column-dependent parts of the temperature row into P[N][*].
+    // Constant pressure:
+    //   J_Tm = -(1/cp) (1/W_m) (P_Tm + Wbar Eu + fT cp_m),
+    //   J_TT = -(1/cp) (P_TT/rho + Eu/T + sum cp_k f_k/W_k + fT sum dcp_k Y_k/W_k);
+    // constant volume (C_k = rho Y_k/W_k, no density border; the rank-one
+    // part of d[M]/dC accumulated in UA[N] for this row, UA[k] for row k):
+    //   J_Tm = -(1/cv) (1/W_m) (P_Tm + UA_N + fT cv_m),
+    //   J_TT = -(1/cv) (P_TT/rho + sum cv_k f_k/W_k + fT sum dcp_k Y_k/W_k)
     const int PS = Lds<NP>::PS;
-    if (lane < N) P[N * PS + lane] += x.Wbar * Eu + fT * m.Rgas * th.cpR;
+    const double tb = m.cv ? lds[Lds<NP>::UA + N] : x.Wbar * Eu;
+    if (lane < N) P[N * PS + lane] += tb + fT * m.Rgas * (th.cpR - one);
     if (lane == N) P[N * PS + N] = P[N * PS + N] / x.rho + Eu * x.invT + Scpf + fT * Sdcp;
     if (lane < NP) lds[Lds<NP>::IW + lane] = lane < N ? m.invW()[lane] : 0.0;
     wave_sync();
     const double invcp = 1.0 / x.cp;
     if (lane < N) {
-        // species rows: J_km = (W_k/W_m) P_km + u_k Wbar/W_m, J_kT = (W_k/rho) P_kT + u_k/T
-        rc = RowCoef{Wk, uk * x.Wbar, Wk / x.rho, uk * x.invT};
+        // species rows, constant pressure: J_km = (W_k/W_m) P_km + u_k Wbar/W_m,
+        // J_kT = (W_k/rho) P_kT + u_k/T; constant volume: J_km = (W_k/W_m)
+        // (P_km + UA_k), J_kT = (W_k/rho) P_kT
+        rc = m.cv ? RowCoef{Wk, Wk * ua, Wk / x.rho, 0.0} : RowCoef{Wk, uk * x.Wbar, Wk / x.rho, uk * x.invT};
     } else if (lane == N) {
         rc = RowCoef{-invcp, 0.0, -invcp, 0.0};
     } else {

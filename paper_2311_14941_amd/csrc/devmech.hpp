@@ -35,6 +35,7 @@ struct TroeRec {
 // small.
 struct DevMech {
     int N, R, nt;
+    int cv;  // 1: constant-volume reactor (the per-cell p input is the density)
     double Rgas, lnp0R;  // lnp0R = ln(p0 / Rgas)
     const double *sp;
     const RxRec *rx;

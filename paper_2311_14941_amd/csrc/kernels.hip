@@ -13,12 +13,13 @@
 
 namespace scdev {
 
-template <int NP>
-__global__ void __launch_bounds__(WAVE) k_rhs(DevMech m, int64_t n, const double *T, const double *p,
+template <int NP, bool CV>
+__global__ void __launch_bounds__(WAVE) k_rhs(DevMech mk, int64_t n, const double *T, const double *p,
                                               const double *Y, int64_t ld, const double *dlnA, double *fT,
                                               double *fY)
 {
     extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
     const int lane = threadIdx.x;
     const int64_t c = blockIdx.x;
     if (c >= n) return;
@@ -28,11 +29,12 @@ __global__ void __launch_bounds__(WAVE) k_rhs(DevMech m, int64_t n, const double
     if (lane == m.N) fT[c] = f;
 }
 
-template <int NP>
-__global__ void __launch_bounds__(WAVE) k_jac(DevMech m, int64_t n, const double *T, const double *p,
+template <int NP, bool CV>
+__global__ void __launch_bounds__(WAVE) k_jac(DevMech mk, int64_t n, const double *T, const double *p,
                                               const double *Y, int64_t ld, const double *dlnA, double *J)
 {
     extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
     const int lane = threadIdx.x;
     const int64_t c = blockIdx.x;
     if (c >= n) return;
@@ -50,12 +52,13 @@ __global__ void __launch_bounds__(WAVE) k_jac(DevMech m, int64_t n, const double
     }
 }
 
-template <int NP>
-__global__ void __launch_bounds__(WAVE) k_linsolve(DevMech m, int64_t n, const double *T, const double *p,
+template <int NP, bool CV>
+__global__ void __launch_bounds__(WAVE) k_linsolve(DevMech mk, int64_t n, const double *T, const double *p,
                                                    const double *Y, int64_t ld, const double *dlnA,
                                                    const double *hg, const double *b, double *x)
 {
     extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
     const int lane = threadIdx.x;
     const int64_t c = blockIdx.x;
     if (c >= n) return;
@@ -96,13 +99,14 @@ __device__ void integrate_cell(const DevMech &m, const Opts &o, double *lds, int
     }
 }
 
-template <int NP>
-__global__ void __launch_bounds__(WAVE) k_integrate(DevMech m, Opts o, int64_t n, const double *T0, const double *P,
+template <int NP, bool CV>
+__global__ void __launch_bounds__(WAVE) k_integrate(DevMech mk, Opts o, int64_t n, const double *T0, const double *P,
                                                     const double *Y0, int64_t ld, const double *DT,
                                                     const double *dlnA, double *h_io, double *T1, double *Y1,
                                                     int32_t *status, int32_t *nacc, int32_t *nrej)
 {
     extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
     const int64_t c = blockIdx.x;
     if (c >= n) return;
     integrate_cell<NP>(m, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
@@ -112,8 +116,8 @@ __global__ void __launch_bounds__(WAVE) k_integrate(DevMech m, Opts o, int64_t n
 // from a global counter (optionally through a permutation, e.g. longest dt
 // first) until the queue is drained.  Per-cell arithmetic is identical to the
 // plain kernel, so results are bitwise equal.
-template <int NP>
-__global__ void __launch_bounds__(WAVE) k_integrate_persistent(DevMech m, Opts o, int64_t n, const double *T0,
+template <int NP, bool CV>
+__global__ void __launch_bounds__(WAVE) k_integrate_persistent(DevMech mk, Opts o, int64_t n, const double *T0,
                                                                const double *P, const double *Y0, int64_t ld,
                                                                const double *DT, const double *dlnA, double *h_io,
                                                                double *T1, double *Y1, int32_t *status,
@@ -122,6 +126,7 @@ __global__ void __launch_bounds__(WAVE) k_integrate_persistent(DevMech m, Opts o
                                                                int tile)
 {
     extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
     const int lane = threadIdx.x;
 #pragma unroll 1
     while (true) {
@@ -140,14 +145,15 @@ __global__ void __launch_bounds__(WAVE) k_integrate_persistent(DevMech m, Opts o
 
 // Static mapping (the baseline the queue is compared with): workgroup w owns
 // cells [w*group, (w+1)*group) and integrates them one after another.
-template <int NP>
-__global__ void __launch_bounds__(WAVE) k_integrate_static(DevMech m, Opts o, int64_t n, const double *T0,
+template <int NP, bool CV>
+__global__ void __launch_bounds__(WAVE) k_integrate_static(DevMech mk, Opts o, int64_t n, const double *T0,
                                                            const double *P, const double *Y0, int64_t ld,
                                                            const double *DT, const double *dlnA, double *h_io,
                                                            double *T1, double *Y1, int32_t *status, int32_t *nacc,
                                                            int32_t *nrej, int64_t group)
 {
     extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
     const int64_t c0 = (int64_t)blockIdx.x * group;
     const int64_t c1 = min(c0 + group, n);
 #pragma unroll 1
@@ -175,19 +181,27 @@ __global__ void k_cost(const int32_t *na, const int32_t *nr, int32_t *key, int64
 template <int NP>
 size_t lds_bytes() { return sizeof(double) * Lds<NP>::SIZE; }
 
-#define SC_DISPATCH(np, CALL)                         \
-    switch (np) {                                     \
-    case 16: { constexpr int NPV = 16; CALL; } break; \
-    case 32: { constexpr int NPV = 32; CALL; } break; \
-    case 56: { constexpr int NPV = 56; CALL; } break; \
-    case 64: { constexpr int NPV = 64; CALL; } break; \
-    default: return hipErrorInvalidValue;             \
+// kernel variant by padded size and reactor model (m.cv); SC_KERNEL keeps
+// the template argument list one macro argument of hipLaunchKernelGGL
+#define SC_KERNEL(k) k<NPV, CVV>
+#define SC_CASE(npv, ...)                                                             \
+    case npv:                                                                         \
+        if (m.cv) { constexpr int NPV = npv; constexpr bool CVV = true; __VA_ARGS__; } \
+        else { constexpr int NPV = npv; constexpr bool CVV = false; __VA_ARGS__; }    \
+        break;
+#define SC_DISPATCH(np, ...)                  \
+    switch (np) {                             \
+    SC_CASE(16, __VA_ARGS__)                  \
+    SC_CASE(32, __VA_ARGS__)                  \
+    SC_CASE(56, __VA_ARGS__)                  \
+    SC_CASE(64, __VA_ARGS__)                  \
+    default: return hipErrorInvalidValue;     \
     }
 
 hipError_t launch_rhs(int np, const DevMech &m, int64_t n, const double *T, const double *p, const double *Y,
                       int64_t ld, const double *dlnA, double *fT, double *fY, hipStream_t s)
 {
-    SC_DISPATCH(np, hipLaunchKernelGGL(k_rhs<NPV>, dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s, m, n, T, p,
+    SC_DISPATCH(np, hipLaunchKernelGGL(SC_KERNEL(k_rhs), dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s, m, n, T, p,
                                        Y, ld, dlnA, fT, fY));
     return hipGetLastError();
 }
@@ -195,7 +209,7 @@ hipError_t launch_rhs(int np, const DevMech &m, int64_t n, const double *T, cons
 hipError_t launch_jac(int np, const DevMech &m, int64_t n, const double *T, const double *p, const double *Y,
                       int64_t ld, const double *dlnA, double *J, hipStream_t s)
 {
-    SC_DISPATCH(np, hipLaunchKernelGGL(k_jac<NPV>, dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s, m, n, T, p,
+    SC_DISPATCH(np, hipLaunchKernelGGL(SC_KERNEL(k_jac), dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s, m, n, T, p,
                                        Y, ld, dlnA, J));
     return hipGetLastError();
 }
@@ -204,7 +218,7 @@ hipError_t launch_linsolve(int np, const DevMech &m, int64_t n, const double *T,
                            int64_t ld, const double *dlnA, const double *hg, const double *b, double *x,
                            hipStream_t s)
 {
-    SC_DISPATCH(np, hipLaunchKernelGGL(k_linsolve<NPV>, dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s, m, n,
+    SC_DISPATCH(np, hipLaunchKernelGGL(SC_KERNEL(k_linsolve), dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s, m, n,
                                        T, p, Y, ld, dlnA, hg, b, x));
     return hipGetLastError();
 }
@@ -213,7 +227,7 @@ hipError_t launch_integrate(int np, const DevMech &m, const Opts &o, int64_t n, 
                             const double *Y0, int64_t ld, const double *dt, const double *dlnA, double *h_io,
                             double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr, hipStream_t s)
 {
-    SC_DISPATCH(np, hipLaunchKernelGGL(k_integrate<NPV>, dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s, m, o,
+    SC_DISPATCH(np, hipLaunchKernelGGL(SC_KERNEL(k_integrate), dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s, m, o,
                                        n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr));
     return hipGetLastError();
 }
@@ -224,7 +238,7 @@ hipError_t launch_integrate_persistent(int np, const DevMech &m, const Opts &o, 
                                        int32_t *na, int32_t *nr, unsigned long long *queue, const int32_t *perm,
                                        int tile, int grid, hipStream_t s)
 {
-    SC_DISPATCH(np, hipLaunchKernelGGL(k_integrate_persistent<NPV>, dim3((unsigned)grid), dim3(WAVE),
+    SC_DISPATCH(np, hipLaunchKernelGGL(SC_KERNEL(k_integrate_persistent), dim3((unsigned)grid), dim3(WAVE),
                                        lds_bytes<NPV>(), s, m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na,
                                        nr, queue, perm, tile));
     return hipGetLastError();
@@ -237,7 +251,7 @@ hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int6
 {
     const int64_t group = (n + grid - 1) / grid;
     const unsigned g = (unsigned)((n + group - 1) / group);
-    SC_DISPATCH(np, hipLaunchKernelGGL(k_integrate_static<NPV>, dim3(g), dim3(WAVE), lds_bytes<NPV>(), s, m, o, n,
+    SC_DISPATCH(np, hipLaunchKernelGGL(SC_KERNEL(k_integrate_static), dim3(g), dim3(WAVE), lds_bytes<NPV>(), s, m, o, n,
                                        T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, group));
     return hipGetLastError();
 }
@@ -299,10 +313,10 @@ int persistent_capacity(int np, int device)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
     hipError_t e = hipErrorInvalidValue;
     switch (np) {
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<16>, WAVE, lds_bytes<16>()); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<32>, WAVE, lds_bytes<32>()); break;
-    case 56: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<56>, WAVE, lds_bytes<56>()); break;
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<64>, WAVE, lds_bytes<64>()); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<16, false>, WAVE, lds_bytes<16>()); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<32, false>, WAVE, lds_bytes<32>()); break;
+    case 56: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<56, false>, WAVE, lds_bytes<56>()); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<64, false>, WAVE, lds_bytes<64>()); break;
     default: break;
     }
     return e == hipSuccess ? per_cu * cus : 0;

@@ -7,7 +7,9 @@ the parity tolerance in every component (else one level tighter) (relative 1e-6 
 fractions above 1e-8, absolute 1e-12 below); see reference() for the
 per-cell choice of level.
 
-Run:  python tests/golden/make_golden.py
+Run:  python tests/golden/make_golden.py           (C1, C2: constant pressure)
+      python tests/golden/make_golden.py constv    (C2 sample as constant-volume
+                                                    reactors: c2v_ref.npz)
 """
 import os
 import sys
@@ -35,12 +37,12 @@ ACCEPT = 5e-2  # consecutive levels must agree to this fraction of the tolerance
 MAX_STEPS = 20000
 
 
-def reference(o, T, p, Y, dt):
+def reference(o, T, p, Y, dt, constv=False):
     """Per cell, the tightest level that succeeds and agrees with the level
     below it to ACCEPT of the parity tolerance.  (Hot equilibrated cells can
     fail at 1e-11: the roundoff of their large forward and reverse rates
     exceeds that tolerance, so those cells use the 1e-10 level.)"""
-    runs = [o.integrate(T, p, Y, dt, rtol=r, atol=a, max_steps=MAX_STEPS) for r, a in LEVELS]
+    runs = [o.integrate(T, p, Y, dt, rtol=r, atol=a, max_steps=MAX_STEPS, constv=constv) for r, a in LEVELS]
     n = T.shape[0]
     Tref, Yref = np.empty(n), np.empty_like(Y)
     level = np.full(n, -1)
@@ -78,5 +80,23 @@ def main():
     print(out)
 
 
+def main_constv():
+    """The C2 stratified sample (16 cells per class, seed 11) as rigid
+    vessels: each cell's density is that of its (p, T0, Y0) state."""
+    from synth.mechgen import R_GAS
+    c2 = make_cells("C2")
+    o2 = Oracle(c2["mech"].to_text())
+    idx = stratified(c2["cls"], 16, seed=11)
+    W = c2["mech"].molar_masses()
+    rho = c2["p"][idx] / (R_GAS * c2["T"][idx] * (c2["Y"][idx] / W).sum(1))
+    ref, conv = reference(o2, c2["T"][idx], rho, c2["Y"][idx], c2["dt"][idx], constv=True)
+    np.savez_compressed(os.path.join(HERE, "c2v_ref.npz"), idx=idx, rho=rho, T=ref["T"], Y=ref["Y"],
+                        level=ref["level"], n_acc=ref["n_acc"], conv=conv)
+    print({"c2v": conv})
+
+
 if __name__ == "__main__":
-    main()
+    if sys.argv[1:] == ["constv"]:
+        main_constv()
+    else:
+        main()
