@@ -82,6 +82,19 @@ typedef enum {
     SC_REACTOR_CONST_V = 1
 } sc_reactor;
 
+/* Integration method of sc_integrate.  ROS4: the 4-stage, order-4
+ * L-stable Rosenbrock method with an embedded order-3 estimate (one
+ * Jacobian, one factorisation and three right-hand sides per step).
+ * EXTRAP: a standard extrapolation baseline, the linearly implicit Euler
+ * method on the step-number sequence 1, 2, 3, 4 with Aitken-Neville
+ * extrapolation to order 4, error from the order-3 entry (four
+ * factorisations, ten substeps per step).  Both use the same analytical
+ * Jacobian and step controller; sc_adjoint supports ROS4 only. */
+typedef enum {
+    SC_METHOD_ROS4 = 0,
+    SC_METHOD_EXTRAP = 1
+} sc_method;
+
 typedef struct {
     double rtol;        /* relative tolerance (default 1e-6) */
     double atol;        /* absolute tolerance, every component (default 1e-12) */
@@ -99,6 +112,7 @@ typedef struct {
                            steps also resolve how perturbations relax, which the
                            adjoint's gradients then follow (see sc_adjoint) */
     int32_t reactor;    /* SC_REACTOR_CONST_P (default) or SC_REACTOR_CONST_V */
+    int32_t method;     /* SC_METHOD_ROS4 (default) or SC_METHOD_EXTRAP */
 } sc_options;
 
 typedef struct {

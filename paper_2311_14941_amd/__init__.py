@@ -25,6 +25,7 @@ CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_BAD_INPUT = rang
 MODES = {"plain": 0, "persistent": 1, "static": 2}
 ORDERS = {"none": 0, "dt": 1, "cost": 2}
 REACTORS = {"const_p": 0, "const_v": 1}
+METHODS = {"ros4": 0, "extrap": 1}
 
 
 class StiffchemError(RuntimeError):
@@ -37,7 +38,7 @@ class Options(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32),
                 ("mode", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32),
                 ("order", C.c_int32), ("fixed_step", C.c_int32), ("hmax_frac", C.c_double),
-                ("reactor", C.c_int32)]
+                ("reactor", C.c_int32), ("method", C.c_int32)]
 
 
 class MechInfo(C.Structure):
@@ -142,11 +143,13 @@ class Plan:
     """A mechanism on one device with integration options.
 
     reactor: "const_p" (the per-cell p arguments are pressures) or "const_v"
-    (a rigid vessel: they are densities in kg/m^3; forward calls only)."""
+    (a rigid vessel: they are densities in kg/m^3; forward calls only).
+    method: "ros4" (the Rosenbrock method) or "extrap" (the linearly implicit
+    Euler extrapolation baseline; forward only)."""
 
     def __init__(self, mech: Mechanism, device: int = 0, rtol=1e-6, atol=1e-12, max_steps=100000,
                  mode="plain", tile=1, grid=0, order="none", fixed_step=False, hmax_frac=0.0,
-                 reactor="const_p"):
+                 reactor="const_p", method="ros4"):
         import torch
         self.torch = torch
         self.mech = mech
@@ -158,7 +161,8 @@ class Plan:
         opt.fixed_step = 1 if fixed_step else 0
         opt.hmax_frac = float(hmax_frac)
         opt.reactor = REACTORS[reactor]
-        self.reactor = reactor
+        opt.method = METHODS[method]
+        self.reactor, self.method = reactor, method
         self.config = dict(mode=mode, tile=tile, grid=grid, order=order)
         self.options = opt
         h = _P()

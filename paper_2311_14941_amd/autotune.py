@@ -31,14 +31,15 @@ def _key(mech, n, torch, device, rtol, atol):
 
 
 def tune(mech, T, p, Y, dt, device=0, rtol=1e-6, atol=1e-12, candidates=CANDIDATES, reps=2,
-         use_cache=True, verbose=False, reactor="const_p"):
+         use_cache=True, verbose=False, reactor="const_p", method="ros4"):
     """Returns (best config dict, {config name: ms}).  Every candidate must give
     bitwise identical results (the per-cell arithmetic does not depend on the
     launch); the tuner checks that and raises if not."""
     import torch
 
     from . import Plan
-    key = _key(mech, T.shape[0], torch, device, rtol, atol) + ("" if reactor == "const_p" else "/" + reactor)
+    key = _key(mech, T.shape[0], torch, device, rtol, atol) + ("" if reactor == "const_p" else "/" + reactor) + (
+        "" if method == "ros4" else "/" + method)
     cache = {}
     if use_cache and os.path.exists(CACHE):
         with open(CACHE) as f:
@@ -48,7 +49,7 @@ def tune(mech, T, p, Y, dt, device=0, rtol=1e-6, atol=1e-12, candidates=CANDIDAT
     times, ref = {}, None
     prev = None
     for cfg in candidates:
-        plan = Plan(mech, device=device, rtol=rtol, atol=atol, reactor=reactor, **cfg)
+        plan = Plan(mech, device=device, rtol=rtol, atol=atol, reactor=reactor, method=method, **cfg)
         out = None
         if cfg["order"] == "cost":
             # measured cost of a previous call on the same cells

@@ -138,6 +138,7 @@ void sc_default_options(sc_options *opt)
     opt->grid = 0;
     opt->order = 0;
     opt->reactor = SC_REACTOR_CONST_P;
+    opt->method = SC_METHOD_ROS4;
 }
 
 sc_status sc_mech_load(const char *text, size_t len, sc_mech **out)
@@ -218,6 +219,7 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
     if (o.fixed_step != 0 && o.fixed_step != 1) return fail(SC_EINVAL, "fixed_step must be 0 or 1");
     if (!(o.hmax_frac >= 0.0) || !std::isfinite(o.hmax_frac)) return fail(SC_EINVAL, "hmax_frac must be >= 0");
     if (o.reactor != SC_REACTOR_CONST_P && o.reactor != SC_REACTOR_CONST_V) return fail(SC_EINVAL, "unknown reactor");
+    if (o.method != SC_METHOD_ROS4 && o.method != SC_METHOD_EXTRAP) return fail(SC_EINVAL, "unknown method");
     DeviceGuard g(device);
     if (!g.ok) return fail(SC_EHIP, "hipSetDevice failed");
     sc_plan *p = nullptr;
@@ -371,18 +373,18 @@ sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double 
         }
         e = scdev::launch_zero_u64(plan->queue, st);
         if (e == hipSuccess)
-            e = scdev::launch_integrate_persistent(plan->np, plan->dm, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1,
-                                                   Y1, cell_status, n_acc, n_rej, plan->queue, perm, tile,
-                                                   grid, st);
+            e = scdev::launch_integrate_persistent(plan->np, plan->dm, o, plan->opt.method, n, T0, p, Y0, ld, dt,
+                                                   dlnA, h_io, T1, Y1, cell_status, n_acc, n_rej, plan->queue,
+                                                   perm, tile, grid, st);
     } else if (plan->opt.mode == SC_MODE_STATIC) {
         int grid = plan->opt.grid > 0 ? plan->opt.grid : plan->capacity;
         if (grid <= 0) grid = 1;
         if (grid > n) grid = (int)n;
-        e = scdev::launch_integrate_static(plan->np, plan->dm, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1,
-                                           cell_status, n_acc, n_rej, grid, st);
+        e = scdev::launch_integrate_static(plan->np, plan->dm, o, plan->opt.method, n, T0, p, Y0, ld, dt, dlnA,
+                                           h_io, T1, Y1, cell_status, n_acc, n_rej, grid, st);
     } else {
-        e = scdev::launch_integrate(plan->np, plan->dm, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, cell_status,
-                                    n_acc, n_rej, st);
+        e = scdev::launch_integrate(plan->np, plan->dm, o, plan->opt.method, n, T0, p, Y0, ld, dt, dlnA, h_io, T1,
+                                    Y1, cell_status, n_acc, n_rej, st);
     }
     return e == hipSuccess ? SC_OK : hip_fail(e, "integrate launch");
 }
@@ -421,6 +423,8 @@ sc_status sc_adjoint(sc_plan *plan, int64_t n, const double *T0, const double *p
     sc_status s = check_common(plan, n, ld, {T0, p, Y0, dt, gT1, gY1, gT0, gY0, cell_status});
     if (s != SC_OK) return s;
     if (plan->dm.cv) return fail(SC_EUNSUPPORTED, "the adjoint supports the constant-pressure reactor only");
+    if (plan->opt.method != SC_METHOD_ROS4)
+        return fail(SC_EUNSUPPORTED, "the adjoint supports the Rosenbrock method only");
     const int R = plan->dm.R;
     hipStream_t st = (hipStream_t)stream;
     DeviceGuard g(plan->device);

@@ -737,6 +737,64 @@ __device__ double ros_attempt(const DevMech &m, const Opts &o, double *lds, doub
     return ynew;
 }
 
+// One step of the extrapolation baseline: the linearly implicit Euler method
+//   (I - h J(y0)) (y_{i+1} - y_i) = h f(y_i),  h = H / n_j,
+// on the step numbers n_j = j (j = 1..EXK), each column's end state T_{j,1}
+// extrapolated to h -> 0 by Aitken-Neville for an expansion in powers of h,
+//   T_{j,l+1} = T_{j,l} + (T_{j,l} - T_{j-1,l}) (j - l) / l.
+// T_{EXK,EXK} is the new state (order EXK); T_{EXK,EXK} - T_{EXK,EXK-1} the
+// error estimate (order EXK - 1 local error, so the controller's
+// err^(-1/4) matches EXK = 4).  The LDS term region holds one matrix, so
+// each column recomputes J(y0) before factorising I/h - J (the same
+// Jacobian: the pass is deterministic).  Row j of the tableau overwrites
+// row j - 1 in the stage-vector area U.
+constexpr int EXK = 4;
+template <int NP>
+__device__ double extrap_attempt(const DevMech &m, const Opts &o, double *lds, double y, double p,
+                                 const double *dlnA, int lane, double H, double *err)
+{
+    const int n = m.N + 1;
+    double *U = lds + Lds<NP>::U;
+    double *F = lds + Lds<NP>::P;
+    double tkk = y, tk1 = y;
+#pragma unroll 1
+    for (int j = 1; j <= EXK; ++j) {
+        RowCoef rc;
+        const double f0 = rhs_jac<NP>(m, lds, y, p, dlnA, lane, rc);
+        const double h = H / j;
+        const double dinv = factor_matrix<NP>(m, lds, rc, lane, 1.0 / h, F);
+        double yi = y, fi = f0;
+#pragma unroll 1
+        for (int i = 0; i < j; ++i) {
+            if (i > 0) fi = rhs<NP>(m, lds, yi, p, dlnA, lane);
+            if (lane >= n) fi = 0.0;
+            yi += lu_solve<NP>(F, dinv, fi, lane);
+        }
+        // row j of the tableau from row j - 1 (U[l-1] holds T_{j-1,l})
+        double t = yi;
+#pragma unroll 1
+        for (int l = 1; l < j; ++l) {
+            const double told = U[(l - 1) * WAVE + lane];
+            const double next = t + (t - told) * ((double)(j - l) / (double)l);
+            U[(l - 1) * WAVE + lane] = t;
+            t = next;
+        }
+        U[(j - 1) * WAVE + lane] = t;
+        if (j == EXK) {
+            tkk = t;
+            tk1 = U[(EXK - 2) * WAVE + lane];
+        }
+    }
+    double e2 = 0.0;
+    if (lane < n) {
+        const double sc = o.atol + o.rtol * fmax(fabs(y), fabs(tkk));
+        const double r = (tkk - tk1) / sc;
+        e2 = r * r;
+    }
+    *err = sqrt(wave_sum(e2) / n);
+    return lane < n ? tkk : 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
@@ -818,9 +876,10 @@ __device__ __forceinline__ int ctl_end(Ctl &s, const Opts &o, double err, double
 }
 
 // Integrate one cell's state y over [0, dt] (dt > 0) from the initial step
-// h: error-controlled (or fixed) Rosenbrock steps.  Returns the cell status;
-// the controller state (step counts, proposed next step) is left in s.
-template <int NP>
+// h: error-controlled (or fixed) steps of the method METH (SC_METHOD_*).
+// Returns the cell status; the controller state (step counts, proposed
+// next step) is left in s.
+template <int NP, int METH = SC_METHOD_ROS4>
 __device__ int advance(const DevMech &m, const Opts &o, double *lds, double &y, double p, double dt,
                        const double *dlnA, int lane, Ctl &s)
 {
@@ -831,7 +890,11 @@ __device__ int advance(const DevMech &m, const Opts &o, double *lds, double &y, 
         const int st = ctl_begin(s, o, dt, hc, last);
         if (st != SC_CELL_OK) return st;
         double err;
-        const double ynew = ros_attempt<NP>(m, o, lds, lds + Lds<NP>::P, y, p, dlnA, lane, hc, &err);
+        double ynew;
+        if constexpr (METH == SC_METHOD_EXTRAP)
+            ynew = extrap_attempt<NP>(m, o, lds, y, p, dlnA, lane, hc, &err);
+        else
+            ynew = ros_attempt<NP>(m, o, lds, lds + Lds<NP>::P, y, p, dlnA, lane, hc, &err);
         const int r = ctl_end(s, o, err, hc, last, dt);
         if (r < 0) return -r;
         if (r == 1) {

@@ -60,17 +60,17 @@ hipError_t launch_jac(int np, const DevMech &m, int64_t n, const double *T, cons
 hipError_t launch_linsolve(int np, const DevMech &m, int64_t n, const double *T, const double *p,
                            const double *Y, int64_t ld, const double *dlnA, const double *hg, const double *b,
                            double *x, hipStream_t s);
-hipError_t launch_integrate(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0,
-                            const double *p, const double *Y0, int64_t ld, const double *dt, const double *dlnA,
-                            double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr,
-                            hipStream_t s);
-hipError_t launch_integrate_persistent(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0,
-                                       const double *p, const double *Y0, int64_t ld, const double *dt,
-                                       const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st,
-                                       int32_t *na, int32_t *nr, unsigned long long *queue,
+hipError_t launch_integrate(int np, const DevMech &m, const Opts &o, int method, int64_t n,
+                            const double *T0, const double *p, const double *Y0, int64_t ld, const double *dt,
+                            const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na,
+                            int32_t *nr, hipStream_t s);
+hipError_t launch_integrate_persistent(int np, const DevMech &m, const Opts &o, int method, int64_t n,
+                                       const double *T0, const double *p, const double *Y0, int64_t ld,
+                                       const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
+                                       int32_t *st, int32_t *na, int32_t *nr, unsigned long long *queue,
                                        const int32_t *perm, int tile, int grid, hipStream_t s);
-hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0,
-                                   const double *p, const double *Y0, int64_t ld, const double *dt,
+hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int method, int64_t n,
+                                   const double *T0, const double *p, const double *Y0, int64_t ld, const double *dt,
                                    const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st,
                                    int32_t *na, int32_t *nr, int grid, hipStream_t s);
 hipError_t order_cells(int order, int64_t n, const double *dt, const int32_t *na, const int32_t *nr,

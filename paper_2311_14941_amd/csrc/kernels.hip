@@ -72,8 +72,8 @@ __global__ void __launch_bounds__(WAVE) k_linsolve(DevMech mk, int64_t n, const 
     if (lane < nn) x[c * nn + lane] = xx;
 }
 
-// One cell over [0, dt] with the Rosenbrock method and error control.
-template <int NP>
+// One cell over [0, dt] with the method METH and error control.
+template <int NP, int METH>
 __device__ void integrate_cell(const DevMech &m, const Opts &o, double *lds, int64_t c, int lane, const double *T0,
                                const double *P, const double *Y0, int64_t ld, const double *DT, const double *dlnA,
                                double *h_io, double *T1, double *Y1, int32_t *status, int32_t *nacc_out,
@@ -87,7 +87,7 @@ __device__ void integrate_cell(const DevMech &m, const Opts &o, double *lds, int
     if (bad_input(m, y, p, dt, lane)) {
         st = SC_CELL_BAD_INPUT;
     } else if (dt > 0.0) {
-        st = advance<NP>(m, o, lds, y, p, dt, dlnA, lane, s);
+        st = advance<NP, METH>(m, o, lds, y, p, dt, dlnA, lane, s);
     }
     if (lane < N) Y1[(int64_t)lane * ld + c] = y;
     if (lane == N) {
@@ -99,7 +99,7 @@ __device__ void integrate_cell(const DevMech &m, const Opts &o, double *lds, int
     }
 }
 
-template <int NP, bool CV>
+template <int NP, bool CV, int METH>
 __global__ void __launch_bounds__(WAVE) k_integrate(DevMech mk, Opts o, int64_t n, const double *T0, const double *P,
                                                     const double *Y0, int64_t ld, const double *DT,
                                                     const double *dlnA, double *h_io, double *T1, double *Y1,
@@ -109,14 +109,14 @@ __global__ void __launch_bounds__(WAVE) k_integrate(DevMech mk, Opts o, int64_t 
     const DevMech m = fix_reactor<CV>(mk);
     const int64_t c = blockIdx.x;
     if (c >= n) return;
-    integrate_cell<NP>(m, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
+    integrate_cell<NP, METH>(m, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
 }
 
 // Persistent variant: a resident grid; each wave pulls tiles of `tile` cells
 // from a global counter (optionally through a permutation, e.g. longest dt
 // first) until the queue is drained.  Per-cell arithmetic is identical to the
 // plain kernel, so results are bitwise equal.
-template <int NP, bool CV>
+template <int NP, bool CV, int METH>
 __global__ void __launch_bounds__(WAVE) k_integrate_persistent(DevMech mk, Opts o, int64_t n, const double *T0,
                                                                const double *P, const double *Y0, int64_t ld,
                                                                const double *DT, const double *dlnA, double *h_io,
@@ -138,14 +138,14 @@ __global__ void __launch_bounds__(WAVE) k_integrate_persistent(DevMech mk, Opts 
 #pragma unroll 1
         for (int64_t i = (int64_t)base; i < end; ++i) {
             const int64_t c = perm ? (int64_t)perm[i] : i;
-            integrate_cell<NP>(m, o, lds, c, lane, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
+            integrate_cell<NP, METH>(m, o, lds, c, lane, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
         }
     }
 }
 
 // Static mapping (the baseline the queue is compared with): workgroup w owns
 // cells [w*group, (w+1)*group) and integrates them one after another.
-template <int NP, bool CV>
+template <int NP, bool CV, int METH>
 __global__ void __launch_bounds__(WAVE) k_integrate_static(DevMech mk, Opts o, int64_t n, const double *T0,
                                                            const double *P, const double *Y0, int64_t ld,
                                                            const double *DT, const double *dlnA, double *h_io,
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(WAVE) k_integrate_static(DevMech mk, Opts o, i
     const int64_t c1 = min(c0 + group, n);
 #pragma unroll 1
     for (int64_t c = c0; c < c1; ++c)
-        integrate_cell<NP>(m, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
+        integrate_cell<NP, METH>(m, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
@@ -189,6 +189,28 @@ size_t lds_bytes() { return sizeof(double) * Lds<NP>::SIZE; }
         if (m.cv) { constexpr int NPV = npv; constexpr bool CVV = true; __VA_ARGS__; } \
         else { constexpr int NPV = npv; constexpr bool CVV = false; __VA_ARGS__; }    \
         break;
+// integration kernels: also by method (SC_METHOD_*)
+#define SC_KERNEL_I(k) k<NPV, CVV, MV>
+#define SC_CASE_I(npv, ...)                                                                              \
+    case npv:                                                                                            \
+        if (m.cv) {                                                                                      \
+            constexpr int NPV = npv; constexpr bool CVV = true;                                          \
+            if (method == SC_METHOD_EXTRAP) { constexpr int MV = SC_METHOD_EXTRAP; __VA_ARGS__; }       \
+            else { constexpr int MV = SC_METHOD_ROS4; __VA_ARGS__; }                                     \
+        } else {                                                                                         \
+            constexpr int NPV = npv; constexpr bool CVV = false;                                         \
+            if (method == SC_METHOD_EXTRAP) { constexpr int MV = SC_METHOD_EXTRAP; __VA_ARGS__; }       \
+            else { constexpr int MV = SC_METHOD_ROS4; __VA_ARGS__; }                                     \
+        }                                                                                                \
+        break;
+#define SC_DISPATCH_I(np, ...)                \
+    switch (np) {                             \
+    SC_CASE_I(16, __VA_ARGS__)                \
+    SC_CASE_I(32, __VA_ARGS__)                \
+    SC_CASE_I(56, __VA_ARGS__)                \
+    SC_CASE_I(64, __VA_ARGS__)                \
+    default: return hipErrorInvalidValue;     \
+    }
 #define SC_DISPATCH(np, ...)                  \
     switch (np) {                             \
     SC_CASE(16, __VA_ARGS__)                  \
@@ -223,36 +245,37 @@ hipError_t launch_linsolve(int np, const DevMech &m, int64_t n, const double *T,
     return hipGetLastError();
 }
 
-hipError_t launch_integrate(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0, const double *p,
-                            const double *Y0, int64_t ld, const double *dt, const double *dlnA, double *h_io,
-                            double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr, hipStream_t s)
+hipError_t launch_integrate(int np, const DevMech &m, const Opts &o, int method, int64_t n, const double *T0,
+                            const double *p, const double *Y0, int64_t ld, const double *dt, const double *dlnA,
+                            double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr,
+                            hipStream_t s)
 {
-    SC_DISPATCH(np, hipLaunchKernelGGL(SC_KERNEL(k_integrate), dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s, m, o,
-                                       n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr));
+    SC_DISPATCH_I(np, hipLaunchKernelGGL(SC_KERNEL_I(k_integrate), dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s,
+                                         m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr));
     return hipGetLastError();
 }
 
-hipError_t launch_integrate_persistent(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0,
-                                       const double *p, const double *Y0, int64_t ld, const double *dt,
-                                       const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st,
-                                       int32_t *na, int32_t *nr, unsigned long long *queue, const int32_t *perm,
-                                       int tile, int grid, hipStream_t s)
+hipError_t launch_integrate_persistent(int np, const DevMech &m, const Opts &o, int method, int64_t n,
+                                       const double *T0, const double *p, const double *Y0, int64_t ld,
+                                       const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
+                                       int32_t *st, int32_t *na, int32_t *nr, unsigned long long *queue,
+                                       const int32_t *perm, int tile, int grid, hipStream_t s)
 {
-    SC_DISPATCH(np, hipLaunchKernelGGL(SC_KERNEL(k_integrate_persistent), dim3((unsigned)grid), dim3(WAVE),
-                                       lds_bytes<NPV>(), s, m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na,
-                                       nr, queue, perm, tile));
+    SC_DISPATCH_I(np, hipLaunchKernelGGL(SC_KERNEL_I(k_integrate_persistent), dim3((unsigned)grid), dim3(WAVE),
+                                         lds_bytes<NPV>(), s, m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na,
+                                         nr, queue, perm, tile));
     return hipGetLastError();
 }
 
-hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int64_t n, const double *T0,
-                                   const double *p, const double *Y0, int64_t ld, const double *dt,
+hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int method, int64_t n,
+                                   const double *T0, const double *p, const double *Y0, int64_t ld, const double *dt,
                                    const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st,
                                    int32_t *na, int32_t *nr, int grid, hipStream_t s)
 {
     const int64_t group = (n + grid - 1) / grid;
     const unsigned g = (unsigned)((n + group - 1) / group);
-    SC_DISPATCH(np, hipLaunchKernelGGL(SC_KERNEL(k_integrate_static), dim3(g), dim3(WAVE), lds_bytes<NPV>(), s, m, o, n,
-                                       T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, group));
+    SC_DISPATCH_I(np, hipLaunchKernelGGL(SC_KERNEL_I(k_integrate_static), dim3(g), dim3(WAVE), lds_bytes<NPV>(), s,
+                                         m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, group));
     return hipGetLastError();
 }
 
@@ -313,10 +336,22 @@ int persistent_capacity(int np, int device)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
     hipError_t e = hipErrorInvalidValue;
     switch (np) {
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<16, false>, WAVE, lds_bytes<16>()); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<32, false>, WAVE, lds_bytes<32>()); break;
-    case 56: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<56, false>, WAVE, lds_bytes<56>()); break;
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<64, false>, WAVE, lds_bytes<64>()); break;
+    case 16:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<16, false, SC_METHOD_ROS4>,
+                                                         WAVE, lds_bytes<16>());
+        break;
+    case 32:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<32, false, SC_METHOD_ROS4>,
+                                                         WAVE, lds_bytes<32>());
+        break;
+    case 56:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<56, false, SC_METHOD_ROS4>,
+                                                         WAVE, lds_bytes<56>());
+        break;
+    case 64:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_persistent<64, false, SC_METHOD_ROS4>,
+                                                         WAVE, lds_bytes<64>());
+        break;
     default: break;
     }
     return e == hipSuccess ? per_cu * cus : 0;

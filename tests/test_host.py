@@ -227,3 +227,29 @@ def test_small_builders():
     assert iso.species[0].nasa[:6] == iso.species[1].nasa[:6]
     for k in ("plain", "third", "troe"):
         single_reaction_mechanism(k)
+
+
+def test_bench_calls_match_package_signatures():
+    """Every keyword that bench.py passes to Plan, autotune.tune, SplitDriver
+    and the package's functions exists in their signatures (the benchmark
+    itself only runs on a GPU)."""
+    import ast
+    import inspect
+
+    import paper_2311_14941_amd as sc
+    from paper_2311_14941_amd import autotune, driver
+    targets = {"Plan": sc.Plan.__init__, "tune": autotune.tune, "SplitDriver": driver.SplitDriver.__init__,
+               "chem_integrate": sc.chem_integrate, "Chain": sc.Chain.__init__, "transport2d": sc.transport2d}
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    seen = set()
+    for node in ast.walk(ast.parse(src)):
+        if isinstance(node, ast.Call):
+            f = node.func
+            name = f.attr if isinstance(f, ast.Attribute) else getattr(f, "id", None)
+            if name in targets:
+                params = inspect.signature(targets[name]).parameters
+                for kw in node.keywords:
+                    if kw.arg is not None:
+                        assert kw.arg in params, (name, kw.arg)
+                seen.add(name)
+    assert {"Plan", "tune", "SplitDriver"} <= seen
