@@ -176,6 +176,12 @@ def main():
                    "cells": n, "launch": launch, "autotune_sample_ms": tune_ms,
                    "kernel": "k_integrate<56>" if launch["mode"] == "plain" else f"k_integrate_{launch['mode']}<56>",
                    "steps_per_cell_mean": float((nacc + nrej).mean()),
+                   # where the work is: share of attempted steps and mean per cell by class
+                   # (unburnt / near ignition / equilibrated)
+                   "steps_by_class": {name: {"share": float((nacc + nrej)[cells["cls"][idx] == k].sum()
+                                                            / max(1, (nacc + nrej).sum())),
+                                             "mean": float((nacc + nrej)[cells["cls"][idx] == k].mean())}
+                                      for k, name in enumerate(("unburnt", "near_ignition", "equilibrated"))},
                    "accepted_mean": float(nacc.mean()), "rejected_mean": float(nrej.mean()),
                    "gradient_forward_ratio": None},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
