@@ -182,11 +182,23 @@ class Plan:
         x = t.as_tensor(x, dtype=dtype, device=f"cuda:{self.device}")
         return x.contiguous()
 
+    def _cells(self, x, n, name, dtype=None):
+        """A per-cell device array of n entries (a scalar is broadcast).  The
+        kernels index every per-cell array up to n, so shapes are checked
+        here, before any launch."""
+        x = self._dev(x, dtype)
+        if x.dim() == 0:
+            x = x.expand(n).contiguous()
+        if tuple(x.shape) != (n,):
+            raise ValueError(f"{name} must have one entry per cell ({n}), got {tuple(x.shape)}")
+        return x
+
     def _state(self, T, p, Y):
-        T, p, Y = self._dev(T), self._dev(p), self._dev(Y)
+        T, Y = self._dev(T), self._dev(Y)
+        if T.dim() != 1:
+            raise ValueError(f"T must be [n], got {tuple(T.shape)}")
         n = T.shape[0]
-        if p.dim() == 0:
-            p = p.expand(n).contiguous()
+        p = self._cells(p, n, "p")
         if Y.shape != (self.mech.N, n):
             raise ValueError(f"Y must be [N={self.mech.N}, n={n}], got {tuple(Y.shape)}")
         return T, p, Y, n
@@ -223,8 +235,10 @@ class Plan:
         """x with (I/hg - J) x = b per cell; b [n, N+1]."""
         T, p, Y, n = self._state(T, p, Y)
         d = self._dlnA(dlnA)
-        hg = self._dev(hg)
+        hg = self._cells(hg, n, "hg")
         b = self._dev(b)
+        if tuple(b.shape) != (n, self.mech.N + 1):
+            raise ValueError(f"b must be [n, N+1] = [{n}, {self.mech.N + 1}], got {tuple(b.shape)}")
         x = self.torch.empty_like(b)
         _check(lib().sc_linsolve(self._h, n, _ptr(T), _ptr(p), _ptr(Y), n, _ptr(d), _ptr(hg), _ptr(b),
                                  _ptr(x), _stream(self.torch, self.device)))
@@ -234,17 +248,20 @@ class Plan:
         """Integrate every cell over its own dt.  Returns a dict with T, Y,
         status, n_acc, n_rej and (when h is given) the carried step h."""
         T0, p, Y0, n = self._state(T0, p, Y0)
-        dt = self._dev(dt)
-        if dt.dim() == 0:
-            dt = dt.expand(n).contiguous()
+        dt = self._cells(dt, n, "dt")
         d = self._dlnA(dlnA)
-        hio = None if h is None else self._dev(h).clone()
+        hio = None if h is None else self._cells(h, n, "h").clone()
         t = self.torch
         if out is None:
             out = dict(T=t.empty_like(T0), Y=t.empty_like(Y0),
                        status=t.empty(n, dtype=t.int32, device=T0.device),
                        n_acc=t.zeros(n, dtype=t.int32, device=T0.device),
                        n_rej=t.zeros(n, dtype=t.int32, device=T0.device))
+        else:
+            want = dict(T=(n,), Y=(self.mech.N, n), status=(n,), n_acc=(n,), n_rej=(n,))
+            for k, shp in want.items():
+                if tuple(out[k].shape) != shp or not out[k].is_contiguous():
+                    raise ValueError(f"out[{k!r}] must be a contiguous tensor of shape {shp}")
         _check(lib().sc_integrate(self._h, n, _ptr(T0), _ptr(p), _ptr(Y0), n, _ptr(dt), _ptr(d),
                                   _ptr(hio), _ptr(out["T"]), _ptr(out["Y"]), _ptr(out["status"]),
                                   _ptr(out["n_acc"]), _ptr(out["n_rej"]), _stream(t, self.device)))
@@ -257,8 +274,8 @@ class Plan:
         parameter part [R, n]."""
         T, p, Y, n = self._state(T, p, Y)
         d = self._dlnA(dlnA)
-        wT, wY = self._dev(wT), self._dev(wY)
-        if wT.shape != T.shape or wY.shape != Y.shape:
+        wT, wY = self._cells(wT, n, "wT"), self._dev(wY)
+        if wY.shape != Y.shape:
             raise ValueError("w must have the shape of the state")
         gT, gY = self.torch.empty_like(T), self.torch.empty_like(Y)
         gc = self.torch.empty((self.mech.R, n), dtype=self.torch.float64, device=T.device) if per_cell else None
@@ -274,15 +291,13 @@ class Plan:
         when asked, g_dlnA_cell [R, n] and the recorded forward T1, Y1."""
         t = self.torch
         T0, p, Y0, n = self._state(T0, p, Y0)
-        dt = self._dev(dt)
-        if dt.dim() == 0:
-            dt = dt.expand(n).contiguous()
+        dt = self._cells(dt, n, "dt")
         d = self._dlnA(dlnA)
         gT1, gY1 = self._dev(gT1), self._dev(gY1)
         if gT1.shape != T0.shape or gY1.shape != Y0.shape:
             raise ValueError("cotangents must have the shape of the state")
-        h0 = None if h is None else self._dev(h)
-        cst = None if cost is None else self._dev(cost, t.int32)
+        h0 = None if h is None else self._cells(h, n, "h")
+        cst = None if cost is None else self._cells(cost, n, "cost", t.int32)
         dev = T0.device
         out = dict(gT0=t.empty_like(T0), gY0=t.empty_like(Y0),
                    g_dlnA=t.empty(self.mech.R, dtype=t.float64, device=dev),
@@ -312,6 +327,10 @@ def transport2d(nx, ny, q, u, dt, dx, diffusivity, inflow, out=None):
     import torch
     if q.dim() != 2 or q.shape[1] != nx * ny or inflow.shape != (q.shape[0], ny):
         raise ValueError("q must be [ncomp, nx*ny] and inflow [ncomp, ny]")
+    if u.shape != (nx * ny,) or dt.shape != (nx * ny,):
+        raise ValueError("u and dt must have one entry per cell")
+    if out is not None and (out.shape != q.shape or not out.is_contiguous() or out.dtype != torch.float64):
+        raise ValueError("out must be a contiguous float64 tensor shaped like q")
     for t in (q, u, dt, inflow):
         if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
             raise ValueError("transport arrays must be contiguous float64 device tensors")
@@ -383,9 +402,7 @@ class Chain:
         t = plan.torch
         self.plan, self.nsub = plan, nsub
         T0, p, Y0, n = plan._state(T0, p, Y0)
-        dt = plan._dev(dt)
-        if dt.dim() == 0:
-            dt = dt.expand(n).contiguous()
+        dt = plan._cells(dt, n, "dt")
         self.n = n
         self.T = [T0.clone() for _ in range(2)]
         self.Y = [Y0.clone() for _ in range(2)]
