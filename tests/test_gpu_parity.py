@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
-Tolerances (spec bar): integrated T and mass fractions above 1e-8 to
+Tolerances (the parity bar): integrated T and mass fractions above 1e-8 to
 relative 1e-6, mass fractions below to absolute 1e-12, against converged
 oracle references (tests/golden).  Right-hand side and Jacobian: element-wise
 against the oracle's definition and its complex-step Jacobian, scaled by the
