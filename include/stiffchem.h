@@ -166,15 +166,16 @@ sc_status sc_linsolve(sc_plan *plan, int64_t n, const double *T, const double *p
                       int64_t ld, const double *dlnA, const double *hg, const double *b, double *x,
                       void *hip_stream);
 
-/* Integrate n cells over their own dt[c] at constant p[c].
- * With SC_ORDER_COST, n_acc and n_rej are read (as the predicted cost of each
- * cell) before they are overwritten; they must then be non-NULL. 
+/* Integrate n cells over their own dt[c] (reactor model and method from the
+ * plan's options: p[c] is the pressure, or the density of a constant-volume
+ * reactor).  With SC_ORDER_COST, n_acc and n_rej are read (as the predicted
+ * cost of each cell) before they are overwritten; they must then be non-NULL.
  *   in : T0[n], p[n], Y0[N*ld], dt[n], dlnA[R] or NULL,
  *        h_io[n] or NULL (initial step; the last accepted step is written back)
  *   out: T1[n], Y1[N*ld] (may alias T0/Y0), cell_status[n],
  *        n_acc[n], n_rej[n] (NULL allowed)
  * Options come from the plan (rtol, atol, max_steps, mode, tile, grid, order,
- * fixed_step, hmax_frac). */
+ * fixed_step, hmax_frac, reactor, method). */
 sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0,
                        int64_t ld, const double *dt, const double *dlnA, double *h_io, double *T1,
                        double *Y1, int32_t *cell_status, int32_t *n_acc, int32_t *n_rej,

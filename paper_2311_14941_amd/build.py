@@ -61,5 +61,21 @@ def build(force=True, jobs=3):
     return LIB
 
 
+C_CHECK_SRC = os.path.join(ROOT, "tests", "c", "c_abi_check.c")
+C_CHECK = os.path.join(OBJDIR, "c_abi_check")
+
+
+def build_c_check():
+    """The plain-C program that drives the C ABI without Python (used by the
+    GPU tests): gcc, HIP runtime headers, linked against the library."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    _run(["gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", f"-I{rocm}/include", f"-I{INC}",
+          C_CHECK_SRC, "-o", C_CHECK, f"-L{rocm}/lib", "-lamdhip64", f"-L{HERE}", "-lstiffchem",
+          f"-Wl,-rpath,{rocm}/lib", "-Wl,-rpath,$ORIGIN/.."])
+    return C_CHECK
+
+
 if __name__ == "__main__":
     print(build(force="--force" in sys.argv))
+    print(build_c_check())
