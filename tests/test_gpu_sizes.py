@@ -5,7 +5,9 @@ them exactly; N = 24 is a ragged case.  For each: right-hand side, Jacobian
 and vector-Jacobian product against the oracle's definition and complex-step
 derivatives, integration at rtol 1e-10 against the oracle at rtol 1e-11 (the
 parity bar), queue and plain launches bit for bit, and the adjoint's
-recorded forward equal to the integration bit for bit."""
+recorded forward equal to the integration bit for bit; and, for the 32-
+and 64-row adjoint kernels, fixed-step gradients against central
+differences of the CPU map."""
 import numpy as np
 import pytest
 
@@ -126,3 +128,53 @@ def test_size_integration_parity_and_launches(torch, sc, ns):
     assert np.all(adj["status"].cpu().numpy() == 0)
     assert torch.equal(adj["T"], a["T"]) and torch.equal(adj["Y"], a["Y"]), ns
     assert bool(torch.isfinite(adj["g_dlnA"]).all())
+
+
+# interval (and, for 63 species, a 1000 K start) where six fixed steps give
+# a map smooth enough that its central differences agree with themselves at
+# half the step to 1e-5 or better
+@pytest.mark.parametrize("ns,T0,dt", [(31, None, 1e-7), (63, 1000.0, 3e-9)])
+def test_size_adjoint_fixed_steps(torch, sc, ns, T0, dt):
+    """The 32- and 64-row adjoint kernels: gradients of a random weighting of
+    (T1, Y1) with respect to (T0, Y0) and to four random directions in
+    log A, through six fixed steps, against central differences of the CPU
+    fixed-step map (tests/frozen_map.py), which the device map also
+    matches."""
+    from frozen_map import fd_gradient, fixed_map
+    mech, o, T, p, Y = case(ns, ncell=2)
+    if T0 is not None:
+        T = np.full(T.size, T0)
+    N, R = mech.n_species, mech.n_reactions
+    rng = np.random.default_rng(7)
+    dlnA = rng.normal(size=R) * 0.1
+    dt = np.full(T.size, dt)
+    nsteps = 6
+    plan = sc.Plan(sc.Mechanism(mech.to_text()), fixed_step=True, max_steps=1000)
+    Tg, pg, Yg, dtg = _gpu(torch, T, p, Y, dt)
+    h = dtg / nsteps
+    wY = rng.normal(size=(T.size, N)) * 1e2
+    wT = rng.normal(size=T.size) * 1e-2
+    out = plan.integrate(Tg, pg, Yg, dtg, dlnA=dlnA, h=h)
+    r = plan.adjoint(Tg, pg, Yg, dtg, torch.tensor(wT, device="cuda:0"),
+                     torch.tensor(np.ascontiguousarray(wY.T), device="cuda:0"), dlnA=dlnA, h=h,
+                     per_cell=True, forward_out=True)
+    assert torch.equal(r["T"], out["T"]) and torch.equal(r["Y"], out["Y"])
+    assert np.all(r["status"].cpu().numpy() == 0)
+    gT0, gY0 = r["gT0"].cpu().numpy(), r["gY0"].cpu().numpy().T
+    gc = r["g_dlnA_cell"].cpu().numpy()
+    T1, Y1 = out["T"].cpu().numpy(), out["Y"].cpu().numpy().T
+    dirs = rng.normal(size=(4, R))
+    for c in range(T.size):
+        y0 = np.append(Y[c], T[c])
+        hn = dt[c] / nsteps
+        y1 = fixed_map(o, y0, p[c], dt[c], hn, dlnA)
+        scale = np.append(np.maximum(np.abs(y1[:-1]), 1e-8), abs(y1[-1]))
+        assert np.max(np.abs(np.append(Y1[c], T1[c]) - y1) / scale) < 1e-8, (ns, c)
+        w = np.append(wY[c], wT[c])
+        g_fd, gp_fd = fd_gradient(o, y0, p[c], dt[c], hn, w, dlnA, dirs)
+        ref = np.append(g_fd, gp_fd)
+        got = np.append(np.append(gY0[c], gT0[c]), dirs @ gc[:, c])
+        den = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+        err = np.max(np.abs(got - ref) / den)
+        print(f"N={ns} cell {c}: adjoint vs central differences {err:.3g}")
+        assert err < 1e-4, (ns, c, err)
