@@ -251,7 +251,8 @@ size_t sc_adjoint_slot_bytes(const sc_plan *plan);
  * every output is a convex combination of inputs: mass fractions stay in
  * [0, 1] and keep their sum.  out has the layout of in (rows of ld values).
  * Device pointers; out must not alias in.  SC_EINVAL for non-positive
- * sizes, nx*ny*ncomp above 2^40, ld < nx*ny, NULL arrays, in == out,
+ * sizes, nx*ny*ncomp above 256 (2^31 - 1) (one thread per value in a grid of
+ * 256-thread blocks), ld < nx*ny, NULL arrays, in == out,
  * dx <= 0 or diffusivity < 0. */
 sc_status sc_transport2d(int32_t nx, int32_t ny, int32_t ncomp, const double *in, int64_t ld, const double *u,
                          const double *dt, double dx, double diffusivity, const double *inflow, double *out,

@@ -199,6 +199,8 @@ __device__ double step_adjoint(const DevMech &m, double *lds, double y, double p
     // numbers; the factors in the term region are no longer needed, so the
     // derivative arrays live there)
     const int toff = Lds<NP>::P - Lds<NP>::C;
+    static_assert(LdsA<NP>::V + NP + (Lds<NP>::P - Lds<NP>::C) <= Lds<NP>::C,
+                  "dual-pass derivative arrays must stay inside the term region");
 #pragma unroll 1
     for (int i = 0; i < NS; ++i)
         lnew += vjp<NP, Dual>(m, lds, Dual(y, U[i * WAVE + lane]), p, dlnA, WS[i * WAVE + lane], lane, TH, toff);

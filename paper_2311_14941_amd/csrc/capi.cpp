@@ -487,7 +487,9 @@ sc_status sc_transport2d(int32_t nx, int32_t ny, int32_t ncomp, const double *in
                          void *stream)
 {
     if (nx <= 0 || ny <= 0 || ncomp <= 0) return fail(SC_EINVAL, "nx, ny and ncomp must be positive");
-    if ((int64_t)nx * ny * ncomp > ((int64_t)1 << 40))  // one thread per value; grid of 256-thread blocks
+    // one thread per value in 256-thread blocks on a one-dimensional grid,
+    // whose x dimension holds at most 2^31 - 1 blocks
+    if ((int64_t)nx * ny * ncomp > (((int64_t)1 << 31) - 1) * 256)
         return fail(SC_EINVAL, "nx * ny * ncomp too large for one launch");
     if (ld < (int64_t)nx * ny) return fail(SC_EINVAL, "ld must be >= nx * ny");
     if (!in || !u || !dt || !inflow || !out) return fail(SC_EINVAL, "required array pointer is NULL");

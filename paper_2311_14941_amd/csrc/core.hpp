@@ -182,7 +182,11 @@ struct Lds {
     // addresses a stride apart; an odd stride spreads them over the banks
     static constexpr int PS = NP + 1;
     static constexpr int P = 0;          // NP x PS Jacobian terms, later the LU factors (stride NP)
-    static constexpr int C = NP * PS;    // concentrations
+    // the term region is also where the adjoint's dual passes keep the
+    // derivatives of C, G, H, WD and of its own V vector (each at a fixed
+    // offset -C from the value), which ends 8 NP + NS WAVE doubles in
+    static constexpr int PREG = NP * PS > 8 * NP + NS * WAVE ? NP * PS : 8 * NP + NS * WAVE;
+    static constexpr int C = PREG;       // concentrations
     static constexpr int G = C + NP;     // g/RT
     static constexpr int H = G + NP;     // h/RT
     static constexpr int WD = H + NP;    // production-rate accumulator

@@ -160,6 +160,10 @@ void parse(Mech &m, const std::string &text)
                 if (k < 0) throw ParseError("line " + std::to_string(line) + ": unknown species " + t[2 + 2 * i]);
                 double a = to_double(t[3 + 2 * i], line);
                 if (a < 0) throw ParseError("negative third-body efficiency");
+                for (auto &x : last->eff)
+                    if (x.first == k)
+                        throw ParseError("line " + std::to_string(line) + ": duplicate efficiency for species " +
+                                         t[2 + 2 * i]);
                 last->eff.push_back({k, a});
             }
         } else if (key == "TROE") {
@@ -192,6 +196,13 @@ void validate(Mech &m)
             if (bal != 0)
                 throw ParseError("reaction " + std::to_string(j) + " does not balance element " + m.elements[e]);
         }
+        // coefficients after repeated species on a side are merged: the
+        // kernels raise concentrations to integer powers 1..3 only
+        for (const auto *side : {&r.reac, &r.prod})
+            for (auto &x : *side)
+                if (x.second > 3)
+                    throw Unsupported("reaction " + std::to_string(j) + ": species " + m.names[x.first] +
+                                      " has a merged stoichiometric coefficient above 3");
         if ((int)r.reac.size() > MAXSIDE || (int)r.prod.size() > MAXSIDE)
             throw Unsupported("reaction " + std::to_string(j) + ": more than 3 distinct species on a side");
         int enh = 0;

@@ -71,6 +71,29 @@ def test_parse_errors_are_reported():
     assert "balance" in str(e.value) or e.value.code == sc.SC_EPARSE
 
 
+def test_merged_coefficients_and_duplicate_efficiencies_are_rejected():
+    """A side written as 'O 2 O 2' merges to nu = 4, which the kernels' integer
+    powers (1..3) cannot take: SC_EUNSUPPORTED, not a silently wrong rate.
+    Two efficiencies for one species of one reaction are ambiguous: SC_EPARSE."""
+    from synth.mechgen import single_reaction_mechanism
+    good = single_reaction_mechanism("third", eff={3: 2.0}).to_text()
+    sc.Mechanism(good)  # the unmodified text loads
+    lines = good.splitlines()
+    k = next(i for i, l in enumerate(lines) if l.startswith("RX "))
+    t = lines[k].split()
+    # H 2 + H 2 + O <=> OH + 3 H: balanced, but H merges to nu = 4 on the left
+    t = t[:5] + ["3", "H", "2", "H", "2", "O", "1", "2", "OH", "1", "H", "3"]
+    merged = "\n".join(lines[:k] + [" ".join(t)] + lines[k + 1:])
+    with pytest.raises(sc.StiffchemError) as e:
+        sc.Mechanism(merged)
+    assert e.value.code == sc.SC_EUNSUPPORTED and "merged" in str(e.value)
+    dup = good.replace("EFF 1 N2 2.0", "EFF 2 N2 2.0 N2 3.0")
+    assert dup != good
+    with pytest.raises(sc.StiffchemError) as e:
+        sc.Mechanism(dup)
+    assert e.value.code == sc.SC_EPARSE and "duplicate efficiency" in str(e.value)
+
+
 def test_oversized_mechanism_is_unsupported():
     with pytest.raises(sc.StiffchemError) as e:
         sc.Mechanism(standard_mechanism("chon_110").to_text())

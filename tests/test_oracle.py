@@ -169,6 +169,98 @@ def test_troe_limits():
     assert abs(kf / (0.5 * kinf * 10 ** (lFc / (1 + f * f))) - 1) < 1e-12
 
 
+def _troe_broadening(Fc, lgPr, T=1000.0, p=101325.0):
+    """The oracle's broadening factor F = kf / (kinf Pr/(1+Pr)) of the single
+    Troe reaction at centre value Fc and log10 Pr (all efficiencies 1, so
+    [M] = p/(RT)).  Fc is set through (a, T3, T1, T2) = (Fc, ~0, ~inf, ~inf),
+    for which the centre formula reduces to a."""
+    Y = np.array([0.2, 0.3, 0.1, 0.4])
+    Mtot = p / (R_GAS * T)
+    lgA0 = lgPr + 12.0 - 6.0 + 12.0 - math.log10(Mtot)
+    m = single_reaction_mechanism("troe", troe=(lgA0, 0.0, 0.0, Fc, 1e-30, 1e30, 1e30), b=0.0, Ea=0.0,
+                                  log10A=12.0)
+    kf = Oracle(m.to_text()).rates(T, p, Y)[0][0]
+    kinf = 10 ** 12.0 * 1e-6
+    Pr = 10.0 ** lgPr
+    return kf / (kinf * Pr / (1.0 + Pr))
+
+
+@pytest.mark.parametrize("Fc", [0.12, 0.3, 0.55, 0.85])
+def test_troe_broadening_properties(Fc):
+    """Properties of the Troe broadening (Gilbert, Luther & Troe 1983) that
+    pin each of its constants separately, for several centre values:
+    (i) at log10 Pr = -c the curve passes through its centre, F = Fc (pins
+        the two constants of c = -0.4 - 0.67 log10 Fc: two Fc values fix both);
+    (ii) where log10 Pr + c = n/1.14 the width function f is 1, so
+        log F = log Fc / 2 (pins n = 0.75 - 1.27 log10 Fc given c);
+    (iii) where log10 Pr + c = n/0.14 the denominator of f vanishes, f is
+        infinite and F = 1 exactly (pins the 0.14; a wrong value leaves f
+        finite there and F visibly below 1).
+    A mistyped constant moves the point where each property holds."""
+    L = math.log10(Fc)
+    c = -0.4 - 0.67 * L
+    n = 0.75 - 1.27 * L
+    assert abs(_troe_broadening(Fc, -c) / Fc - 1.0) < 1e-12
+    assert abs(math.log10(_troe_broadening(Fc, n / 1.14 - c)) - L / 2.0) < 1e-12
+    assert abs(_troe_broadening(Fc, n / 0.14 - c) - 1.0) < 1e-12
+    # and a nearby point is clearly not at the pole (the check above is sharp)
+    assert abs(_troe_broadening(Fc, 0.9 * n / 0.14 - c) - 1.0) > 1e-5
+
+
+def test_troe_centre_special_cases():
+    """The centre value Fc = (1-a) e^(-T/T3) + a e^(-T/T1) + e^(-T2/T): with
+    a = 0 and T2 -> inf it is e^(-T/T3); with a = 1 and T2 -> inf it is
+    e^(-T/T1); at the centre point (log10 Pr = -c) the oracle's F equals it."""
+    T, p = 1400.0, 101325.0
+    Y = np.array([0.2, 0.3, 0.1, 0.4])
+    Mtot = p / (R_GAS * T)
+    for a, T3, T1, want in ((0.0, 900.0, 1e30, math.exp(-T / 900.0)), (1.0, 1e30, 2500.0, math.exp(-T / 2500.0))):
+        L = math.log10(want)
+        lgPr = 0.4 + 0.67 * L
+        lgA0 = lgPr + 12.0 - 6.0 + 12.0 - math.log10(Mtot)
+        m = single_reaction_mechanism("troe", troe=(lgA0, 0.0, 0.0, a, T3, T1, 1e30), b=0.0, Ea=0.0, log10A=12.0)
+        kf = Oracle(m.to_text()).rates(T, p, Y)[0][0]
+        Pr = 10.0 ** lgPr
+        F = kf / (10 ** 12.0 * 1e-6 * Pr / (1.0 + Pr))
+        assert abs(F / want - 1.0) < 1e-12
+
+
+def test_parameter_derivative_of_rhs(c2):
+    """om_dfdp_cs (d f / d dlnA_j, the parameter part of the adjoint's
+    reference) against (i) central differences of the right-hand side in
+    each dlnA_j and (ii) the closed form that follows from dlnA_j scaling the
+    whole net rate q_j:  d f_k/d dlnA_j = W_k nu_kj q_j / rho and
+    d f_T/d dlnA_j = -(sum_k h_k nu_kj) q_j / (rho cp), with q, rho and cp
+    from om_rates and h_k from om_thermo.  A wrong reaction index, a missing
+    reverse term or a stray factor fails one of them."""
+    cells, o = c2
+    mech = cells["mech"]
+    W = mech.molar_masses()
+    nu = mech.stoich()
+    rng = np.random.default_rng(12)
+    for i in (5, 40, 77):
+        y = _y(cells, i)
+        T, p = cells["T"][i], cells["p"][i]
+        dl = rng.uniform(-0.3, 0.3, mech.n_reactions)
+        F = o.dfdp_cs(y, p, dlnA=dl)
+        eps = 1e-5
+        # roundoff floor of a central difference of f: eps_mach |f| / eps
+        floor = 1e-9 * (np.abs(o.rhs(y, p, dlnA=dl)) + np.abs(F).max(axis=1))
+        for j in rng.choice(mech.n_reactions, 25, replace=False):
+            dp, dm = dl.copy(), dl.copy()
+            dp[j] += eps
+            dm[j] -= eps
+            cd = (o.rhs(y, p, dlnA=dp) - o.rhs(y, p, dlnA=dm)) / (2 * eps)
+            assert np.all(np.abs(cd - F[:, j]) <= 1e-6 * np.abs(F[:, j]) + floor)
+        kf, kr, q, wdot, aux = o.rates(T, p, y[:-1], dlnA=dl)
+        rho, cp = aux[0], aux[1]
+        _, hRT, _ = o.thermo(T)
+        closed_Y = W[:, None] * nu * q[None, :] / rho
+        closed_T = -(hRT * R_GAS * T) @ nu * q / (rho * cp)
+        assert np.allclose(F[:-1], closed_Y, rtol=1e-10, atol=1e-12 * np.abs(closed_Y).max())
+        assert np.allclose(F[-1], closed_T, rtol=1e-10, atol=1e-12 * np.abs(closed_T).max())
+
+
 @pytest.mark.parametrize("key", ["h2_9", "chon_53", "chon_110"])
 def test_mass_and_element_conservation_of_rates(key):
     """sum_k W_k wdot_k = 0 and sum_k a_ek wdot_k = 0 for every element at random
