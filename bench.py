@@ -55,9 +55,20 @@ def cpu_baseline(cells, budget_s=15.0, constv=False):
         t_used += time.perf_counter() - t0
         done += idx.size
         assert np.all(r["status"] == 0)
-    return dict(value=done / t_used, unit="cells/s", cores=threads, kind="oracle",
+    return dict(value=done / t_used, unit="cells/s", cores=threads, kind="oracle", cpu_model=cpu_model(),
                 sample=f"{done} cells stratified over the three classes of the same batch (seed 5), "
                        f"{t_used:.1f} s of CPU wall time on {threads} threads, rtol 1e-6 atol 1e-12")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -71,6 +82,8 @@ def main():
     ap.add_argument("--order", default="none", choices=["none", "dt", "cost"],
                     help="persistent mode: cell order (cost: the previous call's step counts)")
     ap.add_argument("--tile", type=int, default=1)
+    ap.add_argument("--linalg", default="auto", choices=["auto", "dense", "sparse"],
+                    help="linear algebra of the implicit stages (auto: dense up to 63 species)")
     ap.add_argument("--method", default="ros4", choices=["ros4", "extrap"],
                     help="c2/c2v: integration method (extrap: the extrapolation baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -120,23 +133,41 @@ def main():
     Y = torch.tensor(np.ascontiguousarray(cells["Y"][idx].T), dtype=torch.float64, device=dev)
     dt = torch.tensor(cells["dt"][idx], dtype=torch.float64, device=dev)
     mech = sc.Mechanism(cells["mech"].to_text())
+    reactor = "const_v" if constv else "const_p"
+    # predicted per-cell work for the cost order: the step counts of a
+    # perturbed copy of the batch (T0 and p within +-1%), standing in for the
+    # previous operator-split substep's counts; never the batch's own counts
+    log("bench: predicted cost from a perturbed copy of the batch")
+    pred = predicted_cost(sc, torch, mech, T, p, Y, dt, reactor, args.method)
     if args.mode == "auto":
         from paper_2311_14941_amd import autotune
         log("bench: autotuning the launch configuration on a 16,384-cell sample")
         s_ = torch.tensor(np.random.default_rng(0).choice(n, 16384, replace=False), device=dev)
         launch, tune_ms = autotune.tune(mech, T[s_].contiguous(), p[s_].contiguous(), Y[:, s_].contiguous(),
-                                        dt[s_].contiguous(), use_cache=False, reps=1,
-                                        reactor="const_v" if constv else "const_p", method=args.method)
+                                        dt[s_].contiguous(), use_cache=False, reps=1, reactor=reactor,
+                                        method=args.method, linalg=args.linalg,
+                                        cost=(pred[0][s_].contiguous(),
+                                                                  pred[1][s_].contiguous()))
     else:
         launch = dict(mode=args.mode, tile=args.tile, grid=0, order=args.order)
         tune_ms = None
-    reactor = "const_v" if constv else "const_p"
-    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, method=args.method, **launch)
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, method=args.method, linalg=args.linalg, **launch)
+    use_pred = launch["mode"] == "persistent" and launch["order"] == "cost"
     stream = torch.cuda.current_stream()
     out = None
+
+    def run_once(o_):
+        if use_pred and o_ is not None:
+            o_["n_acc"].copy_(pred[0])
+            o_["n_rej"].copy_(pred[1])
+        return plan.integrate(T, p, Y, dt, out=o_)
+
     log(f"bench: warmup {args.warmup}")
-    for _ in range(args.warmup):
-        out = plan.integrate(T, p, Y, dt, out=out)
+    out = plan.integrate(T, p, Y, dt, out=dict(T=torch.empty_like(T), Y=torch.empty_like(Y),
+                                                status=torch.empty(n, dtype=torch.int32, device=dev),
+                                                n_acc=pred[0].clone(), n_rej=pred[1].clone()))
+    for _ in range(max(0, args.warmup - 1)):
+        out = run_once(out)
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} steps")
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -144,7 +175,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         evs[i][0].record(stream)
-        out = plan.integrate(T, p, Y, dt, out=out)
+        out = run_once(out)
         evs[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -152,8 +183,9 @@ def main():
     st = out["status"].cpu().numpy()
     nacc = out["n_acc"].cpu().numpy().astype(np.int64)
     nrej = out["n_rej"].cpu().numpy().astype(np.int64)
-    if not np.all(st == 0):
-        log(f"bench: WARNING {np.sum(st != 0)} cells failed: {np.bincount(st)}")
+    failed = int(np.sum(st != 0))
+    if failed:
+        log(f"bench: WARNING {failed} cells failed: {np.bincount(st)}")
     ms_per_step = wall * 1e3 / args.steps
     value = n / (wall / args.steps)
     # algorithmic FP64 work of one launch: every attempted step costs the
@@ -174,7 +206,10 @@ def main():
                                "(unburnt/near-ignition/equilibrated), dt 1e-4 s, rtol 1e-6, atol 1e-12" + (
                                    "; constant-volume reactors at each cell's initial density" if constv else ""),
                    "cells": n, "launch": launch, "autotune_sample_ms": tune_ms,
-                   "kernel": "k_integrate<56>" if launch["mode"] == "plain" else f"k_integrate_{launch['mode']}<56>",
+                   "failed_cells": failed,
+                   "cost_order_counts": ("predicted: step counts of a perturbed copy of the batch (T0, p within "
+                                         "+-1%), copied in before every timed call" if use_pred else None),
+                   "kernel": kernel_name(launch, args.linalg, mech.N), "linalg": args.linalg,
                    "steps_per_cell_mean": float((nacc + nrej).mean()),
                    # where the work is: share of attempted steps and mean per cell by class
                    # (unburnt / near ignition / equilibrated)
@@ -190,41 +225,192 @@ def main():
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None if constv else measured_traffic(launch),
                      "kernel_ms": kern_s * 1e3, "flops_per_launch": flops},
     }
-    if launch["mode"] != "plain":
-        # the same batch through the plain one-workgroup-per-cell launch, for comparison
-        pp = sc.Plan(mech, rtol=1e-6, atol=1e-12, mode="plain", reactor=reactor, method=args.method)
+    # the same batch through the other launches (results bitwise equal):
+    # plain one-workgroup-per-cell, the queue in index order, and the queue
+    # ordered by the batch's own exact counts (an upper bound: a real call
+    # cannot know them)
+    variants = {}
+    for name, cfg, counts in (("plain", dict(mode="plain"), None),
+                              ("persistent_index_order", dict(mode="persistent", order="none"), None),
+                              ("persistent_cost_exact_upper_bound", dict(mode="persistent", order="cost"),
+                               (out["n_acc"].clone(), out["n_rej"].clone()))):
+        pp = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, method=args.method, linalg=args.linalg, **cfg)
         o2 = pp.integrate(T, p, Y, dt)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        o2 = pp.integrate(T, p, Y, dt, out=o2)
-        b.record(stream)
-        torch.cuda.synchronize()
-        res["config"]["plain_launch_ms"] = a.elapsed_time(b)
-        res["config"]["plain_launch_identical"] = bool(torch.equal(o2["T"], out["T"]) and torch.equal(o2["Y"], out["Y"]))
+        ms = []
+        for _ in range(2):
+            if counts is not None:
+                o2["n_acc"].copy_(counts[0])
+                o2["n_rej"].copy_(counts[1])
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            o2 = pp.integrate(T, p, Y, dt, out=o2)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        variants[name] = {"ms": min(ms), "identical": bool(torch.equal(o2["T"], out["T"]) and
+                                                            torch.equal(o2["Y"], out["Y"]))}
+    res["config"]["launch_variants"] = variants
+    res["config"]["plain_launch_ms"] = variants["plain"]["ms"]
+    # host-to-host: state from host memory, integrate, results back to host
+    res["config"]["host_to_host_ms"] = host_to_host_ms(torch, plan, cells, idx, dev, pred if use_pred else None)
+    if not constv and args.method == "ros4":
+        log("bench: parity of the timed output against the stored oracle reference")
+        res["parity"] = parity_block(sc, torch, mech, cells, idx, out, T, p, Y, dt, reactor, args)
     if not args.no_gradient:
         log("bench: gradient/forward ratio on the 16,384-cell batch")
         grad = gradient_ratio(sc, torch, mech_text=cells["mech"].to_text(), launch=launch)
         res["config"]["gradient_forward_ratio"] = grad["ratio"]
         res["gradient"] = grad
+        # the setting whose gradients the forward-sensitivity test validates:
+        # steps capped at dt/32, forward and adjoint alike
+        log("bench: gradient/forward ratio with steps capped at dt/32")
+        res["gradient"]["steps_capped_dt_over_32"] = gradient_ratio(sc, torch, mech_text=cells["mech"].to_text(),
+                                                                    launch=launch, hmax_frac=1.0 / 32)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(cells, constv=constv)
     print(json.dumps(res), flush=True)
 
 
+def predicted_cost(sc, torch, mech, T, p, Y, dt, reactor, method):
+    """Per-cell (n_acc, n_rej) of a perturbed copy of the batch: T0 and p each
+    scaled by a seeded factor in [0.99, 1.01].  The cost order sorts by these
+    counts, as it would by the previous operator-split substep's in a flow
+    solver (close to, not equal to, the counts of the call itself)."""
+    g = np.random.default_rng(99)
+    n = T.shape[0]
+    fT = torch.tensor(1.0 + g.uniform(-0.01, 0.01, n), device=T.device)
+    fp = torch.tensor(1.0 + g.uniform(-0.01, 0.01, n), device=T.device)
+    r = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, method=method).integrate(T * fT, p * fp, Y, dt)
+    return r["n_acc"].clone(), r["n_rej"].clone()
+
+
+def host_to_host_ms(torch, plan, cells, idx, dev, pred):
+    """One integration from host arrays: copy the state in, integrate, copy
+    the results out (wall time, synchronous)."""
+    Th, ph = cells["T"][idx], cells["p"][idx]
+    Yh, dth = np.ascontiguousarray(cells["Y"][idx].T), cells["dt"][idx]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = torch.from_numpy(Th).to(dev)
+    p = torch.from_numpy(ph).to(dev)
+    Y = torch.from_numpy(Yh).to(dev)
+    dt = torch.from_numpy(dth).to(dev)
+    o = None
+    if pred is not None:
+        n = T.shape[0]
+        o = dict(T=torch.empty_like(T), Y=torch.empty_like(Y), status=torch.empty(n, dtype=torch.int32, device=dev),
+                 n_acc=pred[0].clone(), n_rej=pred[1].clone())
+    r = plan.integrate(T, p, Y, dt, out=o)
+    T1, Y1, st = r["T"].cpu().numpy(), r["Y"].cpu().numpy(), r["status"].cpu().numpy()
+    ms = (time.perf_counter() - t0) * 1e3
+    assert T1.shape == Th.shape and Y1.shape == Yh.shape and st.shape == Th.shape
+    return ms
+
+
+def parity_excess(T, Y, Tref, Yref):
+    """Per cell: max over components of |error| / tolerance (the parity bar:
+    relative 1e-6 on T and on mass fractions above 1e-8, absolute 1e-12 below;
+    <= 1 passes)."""
+    eT = np.abs(T - Tref) / (1e-6 * np.abs(Tref))
+    big = np.abs(Yref) > 1e-8
+    eY = np.where(big, np.abs(Y - Yref) / (1e-6 * np.abs(Yref) + 1e-300), np.abs(Y - Yref) / 1e-12)
+    return np.maximum(eT, eY.max(1))
+
+
+RTOL_SWEEP = (1e-7, 1e-8, 1e-9, 1e-10)
+
+
+def parity_block(sc, torch, mech, cells, idx, out, T, p, Y, dt, reactor, args):
+    """Parity of the timed run against the converged oracle reference of a
+    stratified 4,098-cell sample of the batch (tests/golden/c2_ref.npz,
+    written by the oracle alone): pass fraction and worst excess at the
+    production tolerance, then the loosest rtol (atol = 1e-6 rtol, the
+    production ratio) at which every sample cell passes, and the whole
+    batch's throughput there."""
+    g = np.load(os.path.join(ROOT, "tests", "golden", "c2_ref.npz"))
+    ref_idx = g["idx"]
+    n = T.shape[0]
+    if n < cells["T"].size or not np.array_equal(idx[ref_idx], ref_idx):
+        return {"note": "batch is not the full 65,536-cell workload; no stored reference for it"}
+    ri = torch.tensor(ref_idx, device=T.device)
+    cls = cells["cls"][ref_idx]
+
+    def summary(T1, Y1, st):
+        ex = parity_excess(T1, Y1, g["T"], g["Y"])
+        ok = st == 0
+        return {"pass_fraction": float(np.mean((ex <= 1.0) & ok)), "worst_excess": float(ex.max()),
+                "p99_excess": float(np.percentile(ex, 99)), "median_excess": float(np.median(ex)),
+                "by_class": {name: {"pass_fraction": float(np.mean(ex[cls == k] <= 1.0)),
+                                    "worst_excess": float(ex[cls == k].max())}
+                             for k, name in enumerate(("unburnt", "near_ignition", "equilibrated"))}}
+
+    res = {"reference": "oracle (Radau IIA, converged to 5e-2 of the bar between rtol 1e-10 and 1e-11), "
+                        f"{ref_idx.size} stratified cells of the batch",
+           "bar": "T and Y > 1e-8 to relative 1e-6, Y <= 1e-8 to absolute 1e-12; excess = error / bar",
+           "production_rtol_1e-6": summary(out["T"][ri].cpu().numpy(), out["Y"][:, ri].cpu().numpy().T,
+                                           out["status"][ri].cpu().numpy())}
+    Ts, ps, Ys, dts = T[ri].contiguous(), p[ri].contiguous(), Y[:, ri].contiguous(), dt[ri].contiguous()
+    sweep, loosest = {}, None
+    for rt in RTOL_SWEEP:
+        r = sc.Plan(mech, rtol=rt, atol=rt * 1e-6, reactor=reactor, max_steps=200000,
+                    linalg=args.linalg).integrate(Ts, ps, Ys, dts)
+        s_ = summary(r["T"].cpu().numpy(), r["Y"].cpu().numpy().T, r["status"].cpu().numpy())
+        sweep[f"{rt:g}"] = {"pass_fraction": s_["pass_fraction"], "worst_excess": s_["worst_excess"]}
+        if s_["pass_fraction"] == 1.0:
+            loosest = rt
+            break
+    res["rtol_sweep_on_sample"] = sweep
+    if loosest is not None:
+        best = None
+        for mode, order in (("persistent", "none"), ("plain", "none")):
+            pl = sc.Plan(mech, rtol=loosest, atol=loosest * 1e-6, reactor=reactor, max_steps=200000, mode=mode,
+                         order=order, linalg=args.linalg)
+            o2 = pl.integrate(T, p, Y, dt)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            o2 = pl.integrate(T, p, Y, dt, out=o2)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            if best is None or ms < best[0]:
+                best = (ms, mode, int((o2["status"] != 0).sum()), float((o2["n_acc"] + o2["n_rej"]).double().mean()))
+        res["loosest_all_pass"] = {"rtol": loosest, "atol": loosest * 1e-6, "value": n / (best[0] / 1e3),
+                                   "unit": "cells/s", "ms": best[0], "launch": best[1], "failed_cells": best[2],
+                                   "steps_per_cell_mean": best[3]}
+    return res
+
+
 KERNEL_SOURCES = ("paper_2311_14941_amd/csrc/core.hpp", "paper_2311_14941_amd/csrc/kernels.hip")
 
 
 def step_flops(info, method):
-    """Algorithmic FP64 flops of one attempted step.  Rosenbrock: the
-    mechanism compiler's count (Jacobian pass with its right-hand side, one
-    factorisation, two more right-hand sides, four solves, control).
-    Extrapolation: one Jacobian pass and factorisation per column (four),
-    six more right-hand sides and ten solves."""
+    """Algorithmic FP64 flops of one attempted step, whichever kernel runs
+    it: the mechanism compiler's count with the linear algebra of its static
+    sparse schedule (the bordered LU and solves as scheduled; a dense kernel
+    does more arithmetic for the same result).  Rosenbrock: Jacobian pass
+    with its right-hand side, one factorisation, two more right-hand sides,
+    four solves, control.  Extrapolation: one Jacobian pass and
+    factorisation per column (four), six more right-hand sides and ten
+    solves."""
     if method == "ros4":
-        return info["flops_step"]
-    return 4 * (info["flops_jac"] + info["flops_lu"]) + 6 * info["flops_rhs"] + 10 * info["flops_solve"]
+        return info["flops_step_sparse"]
+    jac = info["flops_jac"] - 6 * info["n_state"] ** 2 + 20 * info["n_state"]  # border formation, not dense rows
+    return 4 * (jac + info["flops_lu_sparse"]) + 6 * info["flops_rhs"] + 10 * info["flops_solve_sparse"]
+
+
+def kernel_name(launch, linalg, N):
+    """The integration kernel a launch runs (for the profile summaries)."""
+    mode = launch["mode"]
+    if linalg == "sparse" or (linalg == "auto" and N + 1 > 64):
+        vpl = 1 if N + 1 <= 64 else 2
+        return {"plain": f"k_integrate_sp<{vpl}>", "persistent": f"k_integrate_sp_persistent<{vpl}>",
+                "static": f"k_integrate_sp_static<{vpl}>"}[mode]
+    npd = 16 if N + 1 <= 16 else 32 if N + 1 <= 32 else 56 if N + 1 <= 56 else 64
+    return {"plain": f"k_integrate<{npd}>", "persistent": f"k_integrate_persistent<{npd}>",
+            "static": f"k_integrate_static<{npd}>"}[mode]
 
 
 def kernel_digest():
@@ -339,11 +525,12 @@ def bench_chained(args):
     print(json.dumps(line), flush=True)
 
 
-def gradient_ratio(sc, torch, mech_text, launch, reps=3):
+def gradient_ratio(sc, torch, mech_text, launch, reps=3, hmax_frac=0.0):
     """Wall time of sc_adjoint (recording forward + reverse sweep with
     recompute) over that of sc_integrate, same 16,384 cells (53-species
     mechanism, C2 classes, dt 1e-4 s, seed 204) and options; outputs T1 and
-    Y1 of the {N:1, O:1} species, gradients for T0, Y0 and all dlnA."""
+    Y1 of the {N:1, O:1} species, gradients for T0, Y0 and all dlnA.
+    hmax_frac > 0 caps every step (forward and adjoint) at hmax_frac dt."""
     from synth.cells import make_cells
     c = make_cells("C4")
     dev = "cuda:0"
@@ -352,7 +539,7 @@ def gradient_ratio(sc, torch, mech_text, launch, reps=3):
     Y = torch.tensor(np.ascontiguousarray(c["Y"].T), device=dev)
     dt = torch.tensor(c["dt"], device=dev)
     mech = sc.Mechanism(mech_text)
-    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, **launch)
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, hmax_frac=hmax_frac, **launch)
     k_no = next(k for k, s_ in enumerate(c["mech"].species) if s_.comp == {"N": 1, "O": 1})
     gT1 = torch.ones_like(T)
     gY1 = torch.zeros_like(Y)
@@ -376,6 +563,7 @@ def gradient_ratio(sc, torch, mech_text, launch, reps=3):
     adj = timed(lambda: plan.adjoint(T, p, Y, dt, gT1, gY1, cost=cost))
     st = r["status"].cpu().numpy()
     return {"ratio": adj / fwd, "forward_ms": fwd, "adjoint_ms": adj, "cells": int(T.numel()),
+            "hmax_frac": hmax_frac, "steps_per_cell_mean": float((out["n_acc"] + out["n_rej"]).double().mean()),
             "failed_cells": int(np.sum(st != 0)), "peak_workspace_bytes": int(r["peak_bytes"]),
             "g_dlnA_finite": bool(torch.isfinite(r["g_dlnA"]).all().item())}
 

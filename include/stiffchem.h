@@ -95,6 +95,20 @@ typedef enum {
     SC_METHOD_EXTRAP = 1
 } sc_method;
 
+/* Linear algebra of the implicit stages (paper Sec. 2.5: sparse analytical
+ * Jacobian and sparse algebra management of the mechanism).  DENSE: the
+ * (N+1)-square iteration matrix in registers, one row per lane, factorised
+ * in natural order (N <= 63).  SPARSE: the bordered system of order N+2
+ * (species block with its fixed sparsity, then the temperature and density
+ * borders) in LDS, factorised in the mechanism compiler's minimum-degree
+ * order by its static level schedule (N <= 127).  AUTO: dense where it
+ * applies, else sparse. */
+typedef enum {
+    SC_LINALG_AUTO = 0,
+    SC_LINALG_DENSE = 1,
+    SC_LINALG_SPARSE = 2
+} sc_linalg;
+
 typedef struct {
     double rtol;        /* relative tolerance (default 1e-6) */
     double atol;        /* absolute tolerance, every component (default 1e-12) */
@@ -113,6 +127,7 @@ typedef struct {
                            adjoint's gradients then follow (see sc_adjoint) */
     int32_t reactor;    /* SC_REACTOR_CONST_P (default) or SC_REACTOR_CONST_V */
     int32_t method;     /* SC_METHOD_ROS4 (default) or SC_METHOD_EXTRAP */
+    int32_t linalg;     /* SC_LINALG_AUTO (default), SC_LINALG_DENSE or SC_LINALG_SPARSE */
 } sc_options;
 
 typedef struct {
@@ -129,6 +144,16 @@ typedef struct {
     int64_t flops_lu;     /* one factorisation as the kernel schedules it */
     int64_t flops_solve;  /* one forward + back substitution */
     int64_t flops_step;   /* one Rosenbrock step (Jacobian, LU, stages, control) */
+    /* the sparse linear algebra (SC_LINALG_SPARSE), counted from its static
+     * schedule: the bordered system of order N + 2 in minimum-degree order */
+    int32_t nnz_a_sparse;       /* structural entries of the bordered matrix */
+    int32_t nnz_lu_sparse;      /* entries of L + U (with fill) */
+    int32_t lu_levels;          /* levels of the factorisation schedule */
+    int32_t solve_levels;       /* levels of one forward + one backward solve */
+    int64_t lu_updates_sparse;  /* Schur-complement updates of one factorisation */
+    int64_t flops_lu_sparse;    /* one factorisation (division 1, fma 2) */
+    int64_t flops_solve_sparse; /* one solve */
+    int64_t flops_step_sparse;  /* one step with the sparse linear algebra */
 } sc_mech_info;
 
 void sc_default_options(sc_options *opt);
@@ -141,6 +166,25 @@ sc_status sc_mech_load(const char *text, size_t len, sc_mech **out);
 sc_status sc_mech_info_get(const sc_mech *mech, sc_mech_info *out);
 /* index of a species by name, or SC_EINVAL */
 sc_status sc_species_index(const sc_mech *mech, const char *name, int32_t *idx);
+
+/* One array of the mechanism compiler's sparse algebra (paper Sec. 2.5:
+ * sparse analytical Jacobian, sparse algebra management of the mechanism),
+ * host memory, for inspection and tests.  With out == NULL only *bytes is
+ * set (the size); else up to *bytes bytes are copied and *bytes is set to
+ * the size.  Names (element type):
+ *   "perm" (int32: position -> variable; species 0..N-1, N = T, N+1 = the
+ *     border unknown sigma), "pattern" (uint8, N*N species-term pattern),
+ *   "apat" (uint8, (N+2)^2 bordered pattern in positions),
+ *   "erow", "ecol" (int32: row and column position of each L+U entry),
+ *   "lu_b_lvl", "lu_c_lvl", "fw_lvl", "bw_lvl", "tfw_lvl", "tbw_lvl" (int32
+ *     level offsets), "lu_b", "lu_u", "diag" (uint32 items), "lu_c", "fw",
+ *     "bw", "tfw", "tbw" (uint64 items), "rxi" (uint16, RXI entries per
+ *     reaction in mechanism order).
+ * Item encodings: lu_b e_ik | e_kk << 16 (l_ik = a_ik / a_kk); lu_c
+ * e_ij | e_ik << 16 | e_kj << 32 (a_ij -= l_ik u_kj); lu_u e_kj | k << 16
+ * (u_kj /= u_kk); solves i | p << 16 | e << 32 (x_i -= a_e x_p).
+ * SC_EINVAL for an unknown name. */
+sc_status sc_mech_sparse_array(const sc_mech *mech, const char *name, void *out, size_t *bytes);
 void sc_mech_free(sc_mech *mech);
 
 /* Upload a mechanism's tables to a device (hipSetDevice(device) is made
@@ -180,6 +224,23 @@ sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double 
                        int64_t ld, const double *dt, const double *dlnA, double *h_io, double *T1,
                        double *Y1, int32_t *cell_status, int32_t *n_acc, int32_t *n_rej,
                        void *hip_stream);
+
+/* sc_integrate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, options and results (bit for bit: the same kernels), but
+ * the persistent mode's queue counter and cell-ordering workspace live in a
+ * fixed device scratch array of the library (16 MiB per device, resolved on
+ * the first call on each device and held until the process ends) instead of
+ * plan allocations, so no call allocates or frees.  Limit: n <= 262,144
+ * cells (SC_EINVAL beyond).  Every call on one device shares that scratch,
+ * which keeps the last call's contents (the queue counter is cleared by a
+ * kernel at the start of each call): calls that overlap on one device, on
+ * different streams or host threads, race and must be serialised by the
+ * caller.  Plain and static modes use no scratch. */
+sc_status sc_integrate_noalloc(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0,
+                               int64_t ld, const double *dt, const double *dlnA, double *h_io, double *T1,
+                               double *Y1, int32_t *cell_status, int32_t *n_acc, int32_t *n_rej,
+                               void *hip_stream);
 
 /* Vector-Jacobian product of the right-hand side (the transpose of the
  * sc_jacobian matrix applied to a weight): for every cell

@@ -26,6 +26,7 @@ MODES = {"plain": 0, "persistent": 1, "static": 2}
 ORDERS = {"none": 0, "dt": 1, "cost": 2}
 REACTORS = {"const_p": 0, "const_v": 1}
 METHODS = {"ros4": 0, "extrap": 1}
+LINALGS = {"auto": 0, "dense": 1, "sparse": 2}
 
 
 class StiffchemError(RuntimeError):
@@ -38,7 +39,7 @@ class Options(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32),
                 ("mode", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32),
                 ("order", C.c_int32), ("fixed_step", C.c_int32), ("hmax_frac", C.c_double),
-                ("reactor", C.c_int32), ("method", C.c_int32)]
+                ("reactor", C.c_int32), ("method", C.c_int32), ("linalg", C.c_int32)]
 
 
 class MechInfo(C.Structure):
@@ -46,7 +47,10 @@ class MechInfo(C.Structure):
                                          "n_elements", "n_state", "n_padded", "nnz_jac", "nnz_lu",
                                          "n_stages", "rhs_evals_per_step", "exp_per_rhs")] + \
                [(n, C.c_int64) for n in ("flops_rhs", "flops_jac", "flops_lu", "flops_solve",
-                                         "flops_step")]
+                                         "flops_step")] + \
+               [(n, C.c_int32) for n in ("nnz_a_sparse", "nnz_lu_sparse", "lu_levels", "solve_levels")] + \
+               [(n, C.c_int64) for n in ("lu_updates_sparse", "flops_lu_sparse", "flops_solve_sparse",
+                                         "flops_step_sparse")]
 
 
 _lib = None
@@ -66,6 +70,8 @@ def lib():
         L.sc_mech_load.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(_P)]
         L.sc_mech_info_get.argtypes = [_P, C.POINTER(MechInfo)]
         L.sc_species_index.argtypes = [_P, C.c_char_p, C.POINTER(C.c_int32)]
+        L.sc_mech_sparse_array.argtypes = [_P, C.c_char_p, _P, C.POINTER(C.c_size_t)]
+        L.sc_mech_sparse_array.restype = C.c_int
         L.sc_mech_free.argtypes = [_P]
         L.sc_mech_free.restype = None
         L.sc_plan_create.argtypes = [_P, C.c_int, C.POINTER(Options), C.POINTER(_P)]
@@ -75,6 +81,7 @@ def lib():
         L.sc_jacobian.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P]
         L.sc_linsolve.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P]
         L.sc_integrate.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.sc_integrate_noalloc.argtypes = L.sc_integrate.argtypes
         L.sc_vjp.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]
         L.sc_adjoint.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                  _P, _P, _P, _P, C.c_size_t, C.POINTER(C.c_size_t), _P]
@@ -84,7 +91,7 @@ def lib():
         L.sc_adjoint_slot_bytes.argtypes = [_P]
         L.sc_adjoint_slot_bytes.restype = C.c_size_t
         for f in ("sc_mech_load", "sc_mech_info_get", "sc_species_index", "sc_plan_create", "sc_rhs",
-                  "sc_jacobian", "sc_linsolve", "sc_integrate", "sc_vjp", "sc_adjoint"):
+                  "sc_jacobian", "sc_linsolve", "sc_integrate", "sc_integrate_noalloc", "sc_vjp", "sc_adjoint"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -124,6 +131,22 @@ class Mechanism:
         _check(lib().sc_species_index(self._h, name.encode(), C.byref(k)))
         return k.value
 
+    _SPARSE_DTYPES = {"perm": "int32", "pattern": "uint8", "apat": "uint8", "erow": "int32", "ecol": "int32",
+                      "lu_b_lvl": "int32", "lu_c_lvl": "int32", "fw_lvl": "int32", "bw_lvl": "int32",
+                      "tfw_lvl": "int32", "tbw_lvl": "int32", "lu_b": "uint32", "lu_u": "uint32",
+                      "diag": "uint32", "lu_c": "uint64", "fw": "uint64", "bw": "uint64", "tfw": "uint64",
+                      "tbw": "uint64", "rxi": "uint16"}
+
+    def sparse_array(self, name: str):
+        """One array of the compiled sparse algebra (sc_mech_sparse_array) as
+        a NumPy array (host only)."""
+        import numpy as np
+        nb = C.c_size_t(0)
+        _check(lib().sc_mech_sparse_array(self._h, name.encode(), None, C.byref(nb)))
+        a = np.empty(nb.value // np.dtype(self._SPARSE_DTYPES[name]).itemsize, dtype=self._SPARSE_DTYPES[name])
+        _check(lib().sc_mech_sparse_array(self._h, name.encode(), a.ctypes.data_as(C.c_void_p), C.byref(nb)))
+        return a
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h and _lib is not None:
@@ -149,7 +172,7 @@ class Plan:
 
     def __init__(self, mech: Mechanism, device: int = 0, rtol=1e-6, atol=1e-12, max_steps=100000,
                  mode="plain", tile=1, grid=0, order="none", fixed_step=False, hmax_frac=0.0,
-                 reactor="const_p", method="ros4"):
+                 reactor="const_p", method="ros4", linalg="auto"):
         import torch
         self.torch = torch
         self.mech = mech
@@ -162,7 +185,8 @@ class Plan:
         opt.hmax_frac = float(hmax_frac)
         opt.reactor = REACTORS[reactor]
         opt.method = METHODS[method]
-        self.reactor, self.method = reactor, method
+        opt.linalg = LINALGS[linalg]
+        self.reactor, self.method, self.linalg = reactor, method, linalg
         self.config = dict(mode=mode, tile=tile, grid=grid, order=order)
         self.options = opt
         h = _P()
@@ -244,7 +268,14 @@ class Plan:
                                  _ptr(x), _stream(self.torch, self.device)))
         return x
 
-    def integrate(self, T0, p, Y0, dt, dlnA=None, h=None, out=None):
+    def integrate_noalloc(self, T0, p, Y0, dt, dlnA=None, h=None, out=None):
+        """integrate() through sc_integrate_noalloc: the library allocates no
+        device memory in the call (queue and ordering workspace in its fixed
+        scratch; at most 262,144 cells).  Pass `out` (and h) to keep the
+        binding itself from allocating result tensors."""
+        return self.integrate(T0, p, Y0, dt, dlnA=dlnA, h=h, out=out, _entry="sc_integrate_noalloc")
+
+    def integrate(self, T0, p, Y0, dt, dlnA=None, h=None, out=None, _entry="sc_integrate"):
         """Integrate every cell over its own dt.  Returns a dict with T, Y,
         status, n_acc, n_rej and (when h is given) the carried step h."""
         T0, p, Y0, n = self._state(T0, p, Y0)
@@ -262,9 +293,9 @@ class Plan:
             for k, shp in want.items():
                 if tuple(out[k].shape) != shp or not out[k].is_contiguous():
                     raise ValueError(f"out[{k!r}] must be a contiguous tensor of shape {shp}")
-        _check(lib().sc_integrate(self._h, n, _ptr(T0), _ptr(p), _ptr(Y0), n, _ptr(dt), _ptr(d),
-                                  _ptr(hio), _ptr(out["T"]), _ptr(out["Y"]), _ptr(out["status"]),
-                                  _ptr(out["n_acc"]), _ptr(out["n_rej"]), _stream(t, self.device)))
+        _check(getattr(lib(), _entry)(self._h, n, _ptr(T0), _ptr(p), _ptr(Y0), n, _ptr(dt), _ptr(d),
+                                      _ptr(hio), _ptr(out["T"]), _ptr(out["Y"]), _ptr(out["status"]),
+                                      _ptr(out["n_acc"]), _ptr(out["n_rej"]), _stream(t, self.device)))
         if hio is not None:
             out["h"] = hio
         return out

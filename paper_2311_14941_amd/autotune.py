@@ -31,15 +31,20 @@ def _key(mech, n, torch, device, rtol, atol):
 
 
 def tune(mech, T, p, Y, dt, device=0, rtol=1e-6, atol=1e-12, candidates=CANDIDATES, reps=2,
-         use_cache=True, verbose=False, reactor="const_p", method="ros4"):
+         use_cache=True, verbose=False, reactor="const_p", method="ros4", cost=None, linalg="auto"):
     """Returns (best config dict, {config name: ms}).  Every candidate must give
     bitwise identical results (the per-cell arithmetic does not depend on the
-    launch); the tuner checks that and raises if not."""
+    launch); the tuner checks that and raises if not.
+
+    cost: (n_acc, n_rej) per cell, the predicted work the "cost" order sorts
+    by (e.g. the counts of the previous operator-split substep).  Without it
+    the tuner uses the counts of an identical earlier call on the same cells,
+    which are exact: an upper bound of what cost ordering can gain."""
     import torch
 
     from . import Plan
     key = _key(mech, T.shape[0], torch, device, rtol, atol) + ("" if reactor == "const_p" else "/" + reactor) + (
-        "" if method == "ros4" else "/" + method)
+        "" if method == "ros4" else "/" + method) + ("/exact-cost" if cost is None else "/predicted-cost")
     cache = {}
     if use_cache and os.path.exists(CACHE):
         with open(CACHE) as f:
@@ -47,12 +52,14 @@ def tune(mech, T, p, Y, dt, device=0, rtol=1e-6, atol=1e-12, candidates=CANDIDAT
         if key in cache:
             return cache[key]["best"], cache[key]["times"]
     times, ref = {}, None
-    prev = None
+    prev = None if cost is None else {"n_acc": cost[0], "n_rej": cost[1]}
     for cfg in candidates:
-        plan = Plan(mech, device=device, rtol=rtol, atol=atol, reactor=reactor, method=method, **cfg)
+        plan = Plan(mech, device=device, rtol=rtol, atol=atol, reactor=reactor, method=method, linalg=linalg,
+                    **cfg)
         out = None
         if cfg["order"] == "cost":
-            # measured cost of a previous call on the same cells
+            # an output buffer whose counts are overwritten with the predicted
+            # (or an identical earlier call's) counts before every timed call
             out = plan.integrate(T, p, Y, dt)
         best = float("inf")
         for _ in range(reps):
@@ -68,7 +75,8 @@ def tune(mech, T, p, Y, dt, device=0, rtol=1e-6, atol=1e-12, candidates=CANDIDAT
         times[name] = best * 1e3
         if ref is None:
             ref = {k: v.clone() for k, v in out.items()}
-            prev = {"n_acc": ref["n_acc"], "n_rej": ref["n_rej"]}
+            if prev is None:
+                prev = {"n_acc": ref["n_acc"], "n_rej": ref["n_rej"]}
         else:
             for k in ("T", "Y", "status", "n_acc", "n_rej"):
                 if not torch.equal(ref[k], out[k]):

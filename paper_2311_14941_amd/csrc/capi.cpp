@@ -24,6 +24,9 @@ struct sc_plan {
     int device = 0;
     int np = 0;
     scdev::DevMech dm{};
+    bool sparse = false;  // sparse linear algebra kernels
+    int vpl = 1;          // state components per lane of the sparse kernels
+    scdev::DevSparse ds{};
     std::vector<void *> allocs;
     unsigned long long *queue = nullptr;
     int capacity = 0;
@@ -185,6 +188,51 @@ sc_status sc_mech_info_get(const sc_mech *mech, sc_mech_info *out)
     out->flops_lu = m.cnt.flops_lu;
     out->flops_solve = m.cnt.flops_solve;
     out->flops_step = m.cnt.flops_step;
+    out->nnz_a_sparse = (int32_t)m.sp.nnz_a;
+    out->nnz_lu_sparse = m.sp.nnz;
+    out->lu_levels = (int32_t)m.sp.lu_b_lvl.size() - 1;
+    out->solve_levels = (int32_t)(m.sp.fw_lvl.size() + m.sp.bw_lvl.size()) - 2;
+    out->lu_updates_sparse = m.sp.updates;
+    out->flops_lu_sparse = m.cnt_sparse.flops_lu;
+    out->flops_solve_sparse = m.cnt_sparse.flops_solve;
+    out->flops_step_sparse = m.cnt_sparse.flops_step;
+    return SC_OK;
+}
+
+sc_status sc_mech_sparse_array(const sc_mech *mech, const char *name, void *out, size_t *bytes)
+{
+    if (!mech || !name || !bytes) return fail(SC_EINVAL, "NULL argument");
+    const sc::SparseLU &s = mech->m.sp;
+    const void *src = nullptr;
+    size_t sz = 0;
+    auto take = [&](const auto &v) {
+        src = v.data();
+        sz = v.size() * sizeof(v[0]);
+    };
+    const std::string k(name);
+    if (k == "perm") take(s.perm);
+    else if (k == "pattern") take(mech->m.pattern);
+    else if (k == "apat") take(s.apat);
+    else if (k == "erow") take(s.erow);
+    else if (k == "ecol") take(s.ecol);
+    else if (k == "lu_b_lvl") take(s.lu_b_lvl);
+    else if (k == "lu_c_lvl") take(s.lu_c_lvl);
+    else if (k == "lu_b") take(s.lu_b);
+    else if (k == "lu_c") take(s.lu_c);
+    else if (k == "lu_u") take(s.lu_u);
+    else if (k == "diag") take(s.diag);
+    else if (k == "fw_lvl") take(s.fw_lvl);
+    else if (k == "bw_lvl") take(s.bw_lvl);
+    else if (k == "tfw_lvl") take(s.tfw_lvl);
+    else if (k == "tbw_lvl") take(s.tbw_lvl);
+    else if (k == "fw") take(s.fw);
+    else if (k == "bw") take(s.bw);
+    else if (k == "tfw") take(s.tfw);
+    else if (k == "tbw") take(s.tbw);
+    else if (k == "rxi") take(s.rxi);
+    else return fail(SC_EINVAL, "unknown sparse array " + k);
+    if (out && sz) std::memcpy(out, src, std::min(sz, *bytes));
+    *bytes = sz;
     return SC_OK;
 }
 
@@ -220,6 +268,45 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
     if (!(o.hmax_frac >= 0.0) || !std::isfinite(o.hmax_frac)) return fail(SC_EINVAL, "hmax_frac must be >= 0");
     if (o.reactor != SC_REACTOR_CONST_P && o.reactor != SC_REACTOR_CONST_V) return fail(SC_EINVAL, "unknown reactor");
     if (o.method != SC_METHOD_ROS4 && o.method != SC_METHOD_EXTRAP) return fail(SC_EINVAL, "unknown method");
+    if (o.linalg != SC_LINALG_AUTO && o.linalg != SC_LINALG_DENSE && o.linalg != SC_LINALG_SPARSE)
+        return fail(SC_EINVAL, "unknown linalg");
+    const int nstate = mech->m.N + 1;
+    const bool sparse = o.linalg == SC_LINALG_SPARSE || (o.linalg == SC_LINALG_AUTO && nstate > sc::MAX_STATE);
+    if (!sparse && nstate > sc::MAX_STATE)
+        return fail(SC_EUNSUPPORTED, "the dense linear algebra supports up to " + std::to_string(sc::MAX_STATE - 1) +
+                                         " species; use the sparse one (linalg = SC_LINALG_SPARSE or AUTO)");
+    if (sparse && o.method != SC_METHOD_ROS4)
+        return fail(SC_EUNSUPPORTED, "the extrapolation baseline runs with the dense linear algebra only");
+    const int vpl = nstate <= 64 ? 1 : 2;
+    const sc::SparseLU &S = mech->m.sp;
+    scdev::DevSparse ds{};
+    if (sparse) {
+        const int NV = 64 * vpl;
+        ds.n = S.n;
+        ds.nnz = S.nnz;
+        ds.nl_lu = (int)S.lu_b_lvl.size() - 1;
+        ds.nl_fw = (int)S.fw_lvl.size() - 1;
+        ds.nl_bw = (int)S.bw_lvl.size() - 1;
+        ds.n_u = (int)S.lu_u.size();
+        ds.NV = NV;
+        ds.E = 0;
+        ds.C = S.nnz;
+        ds.G = ds.C + NV;
+        ds.H = ds.G + NV;
+        ds.WD = ds.H + NV;
+        ds.UA = ds.WD + NV;
+        ds.U = ds.UA + NV;
+        ds.X = ds.U + 4 * NV;
+        ds.DINV = ds.X + S.n;
+        ds.size = ds.DINV + S.n;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(SC_EHIP, "hipGetDeviceProperties failed");
+        if (sizeof(double) * (size_t)ds.size > prop.sharedMemPerBlock)
+            return fail(SC_EUNSUPPORTED, "the sparse factors of this mechanism need " +
+                                             std::to_string(sizeof(double) * ds.size) +
+                                             " bytes of LDS per cell; the device has " +
+                                             std::to_string(prop.sharedMemPerBlock));
+    }
     DeviceGuard g(device);
     if (!g.ok) return fail(SC_EHIP, "hipSetDevice failed");
     sc_plan *p = nullptr;
@@ -289,6 +376,38 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
                                t.troe[4 * nt + k], t.troe[5 * nt + k], t.troe[6 * nt + k], 0.0};
     }
     bool ok = upload(p, spv, &d.sp) && upload(p, rx, &d.rx) && upload(p, tr, &d.troe);
+    p->sparse = sparse;
+    p->vpl = vpl;
+    p->ds = ds;
+    if (ok && sparse) {
+        const int N = t.N;
+        // per-reaction entry indices in the execution order of the records
+        std::vector<uint16_t> rxi((size_t)t.R * sc::RXI_SIZE);
+        for (int q = 0; q < t.R; ++q)
+            std::memcpy(&rxi[(size_t)q * sc::RXI_SIZE], &S.rxi[(size_t)order[q] * sc::RXI_SIZE],
+                        sizeof(uint16_t) * sc::RXI_SIZE);
+        std::vector<int32_t> comp((size_t)scdev::CMP * (N + 1), -1);
+        for (int k = 0; k < N; ++k) {
+            int32_t *c = &comp[(size_t)scdev::CMP * k];
+            c[0] = S.pos[k];
+            c[1] = S.e_kk[k];
+            c[2] = S.e_kT[k];
+            c[3] = S.e_kS[k];
+            c[4] = S.e_Tk[k];
+            c[5] = S.e_Sk[k];
+        }
+        comp[(size_t)scdev::CMP * N] = S.pos[N];
+        comp[(size_t)scdev::CMP * N + 1] = S.e_TT;
+        comp[(size_t)scdev::CMP * N + 2] = S.e_SS;
+        std::vector<uint16_t> emap(S.emap.size());
+        for (size_t i = 0; i < emap.size(); ++i) emap[i] = S.emap[i] < 0 ? sc::NOENT : (uint16_t)S.emap[i];
+        scdev::DevSparse &q = p->ds;
+        ok = upload(p, S.lu_b_lvl, &q.lu_b_lvl) && upload(p, S.lu_c_lvl, &q.lu_c_lvl) &&
+             upload(p, S.fw_lvl, &q.fw_lvl) && upload(p, S.bw_lvl, &q.bw_lvl) && upload(p, S.lu_b, &q.lu_b) &&
+             upload(p, S.lu_u, &q.lu_u) && upload(p, S.diag, &q.diag) && upload(p, S.lu_c, &q.lu_c) &&
+             upload(p, S.fw, &q.fw) && upload(p, S.bw, &q.bw) && upload(p, rxi, &q.rxi) &&
+             upload(p, comp, &q.comp) && upload(p, emap, &q.emap);
+    }
     if (ok) {
         void *q = nullptr;
         ok = hipMalloc(&q, sizeof(unsigned long long)) == hipSuccess;
@@ -302,8 +421,8 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
         delete p;
         return fail(SC_ENOMEM, "device allocation/upload failed");
     }
-    p->capacity = scdev::persistent_capacity(p->np, device);
-    p->adj_capacity = scdev::adjoint_capacity(p->np, d.R, device);
+    p->capacity = sparse ? scdev::persistent_capacity_sp(vpl, p->ds, device) : scdev::persistent_capacity(p->np, device);
+    p->adj_capacity = nstate <= sc::MAX_STATE ? scdev::adjoint_capacity(p->np, d.R, device) : 0;
     *out = p;
     return SC_OK;
 }
@@ -321,7 +440,10 @@ sc_status sc_rhs(sc_plan *plan, int64_t n, const double *T, const double *p, con
     sc_status s = check_common(plan, n, ld, {T, p, Y, fT, fY});
     if (s != SC_OK || n == 0) return s;
     DeviceGuard g(plan->device);
-    hipError_t e = scdev::launch_rhs(plan->np, plan->dm, n, T, p, Y, ld, dlnA, fT, fY, (hipStream_t)stream);
+    hipError_t e =
+        plan->sparse
+            ? scdev::launch_rhs_sp(plan->vpl, plan->dm, plan->ds, n, T, p, Y, ld, dlnA, fT, fY, (hipStream_t)stream)
+            : scdev::launch_rhs(plan->np, plan->dm, n, T, p, Y, ld, dlnA, fT, fY, (hipStream_t)stream);
     return e == hipSuccess ? SC_OK : hip_fail(e, "rhs launch");
 }
 
@@ -331,7 +453,10 @@ sc_status sc_jacobian(sc_plan *plan, int64_t n, const double *T, const double *p
     sc_status s = check_common(plan, n, ld, {T, p, Y, J});
     if (s != SC_OK || n == 0) return s;
     DeviceGuard g(plan->device);
-    hipError_t e = scdev::launch_jac(plan->np, plan->dm, n, T, p, Y, ld, dlnA, J, (hipStream_t)stream);
+    hipError_t e = plan->sparse
+                       ? scdev::launch_jac_sp(plan->vpl, plan->dm, plan->ds, n, T, p, Y, ld, dlnA, J,
+                                              (hipStream_t)stream)
+                       : scdev::launch_jac(plan->np, plan->dm, n, T, p, Y, ld, dlnA, J, (hipStream_t)stream);
     return e == hipSuccess ? SC_OK : hip_fail(e, "jacobian launch");
 }
 
@@ -341,22 +466,53 @@ sc_status sc_linsolve(sc_plan *plan, int64_t n, const double *T, const double *p
     sc_status s = check_common(plan, n, ld, {T, p, Y, hg, b, x});
     if (s != SC_OK || n == 0) return s;
     DeviceGuard g(plan->device);
-    hipError_t e =
-        scdev::launch_linsolve(plan->np, plan->dm, n, T, p, Y, ld, dlnA, hg, b, x, (hipStream_t)stream);
+    hipError_t e = plan->sparse ? scdev::launch_linsolve_sp(plan->vpl, plan->dm, plan->ds, n, T, p, Y, ld, dlnA, hg,
+                                                            b, x, (hipStream_t)stream)
+                                : scdev::launch_linsolve(plan->np, plan->dm, n, T, p, Y, ld, dlnA, hg, b, x,
+                                                         (hipStream_t)stream);
     return e == hipSuccess ? SC_OK : hip_fail(e, "linsolve launch");
 }
 
-sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0, int64_t ld,
-                       const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
-                       int32_t *cell_status, int32_t *n_acc, int32_t *n_rej, void *stream)
+// sc_integrate and its allocation-free variant: with `noalloc` the queue
+// counter and the ordering workspace come from the library's fixed device
+// scratch instead of the plan's allocations.
+static sc_status integrate_impl(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0, int64_t ld,
+                         const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
+                         int32_t *cell_status, int32_t *n_acc, int32_t *n_rej, void *stream, bool noalloc)
 {
     sc_status s = check_common(plan, n, ld, {T0, p, Y0, dt, T1, Y1, cell_status});
     if (s != SC_OK || n == 0) return s;
     if (plan->opt.fixed_step && !h_io) return fail(SC_EINVAL, "fixed_step needs h_io (the step of each cell)");
+    if (plan->opt.mode == SC_MODE_PERSISTENT && plan->opt.order == SC_ORDER_COST && (!n_acc || !n_rej))
+        return fail(SC_EINVAL, "cost ordering needs the previous n_acc and n_rej");
     DeviceGuard g(plan->device);
     const scdev::Opts o = dev_opts(plan->opt);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
+    unsigned long long *queue = plan->queue;
+    char *ows = nullptr;  // ordering workspace in the fixed scratch
+    size_t ows_bytes = 0;
+    if (noalloc && plan->opt.mode == SC_MODE_PERSISTENT) {
+        void *base = nullptr;
+        size_t bytes = 0;
+        int64_t max_cells = 0;
+        e = scdev::noalloc_scratch(plan->device, &base, &bytes, &max_cells);
+        if (e != hipSuccess) return hip_fail(e, "device scratch address");
+        if (n > max_cells)
+            return fail(SC_EINVAL, "sc_integrate_noalloc: n = " + std::to_string(n) + " exceeds its limit of " +
+                                       std::to_string(max_cells) + " cells");
+        queue = static_cast<unsigned long long *>(base);
+        ows = static_cast<char *>(base) + 256;
+        ows_bytes = bytes - 256;
+        if (plan->opt.order != SC_ORDER_NONE) {
+            size_t need = 0;
+            e = scdev::order_ws_need(plan->opt.order, n, &need, st);
+            if (e != hipSuccess) return hip_fail(e, "ordering workspace size");
+            if (need > ows_bytes)
+                return fail(SC_EINVAL, "sc_integrate_noalloc: the cell ordering of n = " + std::to_string(n) +
+                                           " cells needs more than the fixed scratch holds");
+        }
+    }
     if (plan->opt.mode == SC_MODE_PERSISTENT) {
         const int tile = plan->opt.tile;
         int64_t tiles = (n + tile - 1) / tile;
@@ -364,29 +520,55 @@ sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double 
         if (grid <= 0) grid = 1;
         if (grid > tiles) grid = (int)tiles;
         int32_t *perm = nullptr;
-        if (plan->opt.order == SC_ORDER_COST && (!n_acc || !n_rej))
-            return fail(SC_EINVAL, "cost ordering needs the previous n_acc and n_rej");
         if (plan->opt.order != SC_ORDER_NONE) {
-            e = scdev::order_cells(plan->opt.order, n, dt, n_acc, n_rej, &plan->order_ws, &plan->order_ws_bytes, &perm,
-                                   st);
+            if (noalloc)
+                e = scdev::order_cells_in(plan->opt.order, n, dt, n_acc, n_rej, ows, ows_bytes, &perm, st);
+            else
+                e = scdev::order_cells(plan->opt.order, n, dt, n_acc, n_rej, &plan->order_ws, &plan->order_ws_bytes,
+                                       &perm, st);
             if (e != hipSuccess) return hip_fail(e, "cell ordering");
         }
-        e = scdev::launch_zero_u64(plan->queue, st);
-        if (e == hipSuccess)
+        e = scdev::launch_zero_u64(queue, st);
+        if (e == hipSuccess && plan->sparse)
+            e = scdev::launch_integrate_sp_persistent(plan->vpl, plan->dm, plan->ds, o, n, T0, p, Y0, ld, dt, dlnA,
+                                                      h_io, T1, Y1, cell_status, n_acc, n_rej, queue, perm, tile,
+                                                      grid, st);
+        else if (e == hipSuccess)
             e = scdev::launch_integrate_persistent(plan->np, plan->dm, o, plan->opt.method, n, T0, p, Y0, ld, dt,
-                                                   dlnA, h_io, T1, Y1, cell_status, n_acc, n_rej, plan->queue,
-                                                   perm, tile, grid, st);
+                                                   dlnA, h_io, T1, Y1, cell_status, n_acc, n_rej, queue, perm, tile,
+                                                   grid, st);
     } else if (plan->opt.mode == SC_MODE_STATIC) {
         int grid = plan->opt.grid > 0 ? plan->opt.grid : plan->capacity;
         if (grid <= 0) grid = 1;
         if (grid > n) grid = (int)n;
-        e = scdev::launch_integrate_static(plan->np, plan->dm, o, plan->opt.method, n, T0, p, Y0, ld, dt, dlnA,
-                                           h_io, T1, Y1, cell_status, n_acc, n_rej, grid, st);
+        if (plan->sparse)
+            e = scdev::launch_integrate_sp_static(plan->vpl, plan->dm, plan->ds, o, n, T0, p, Y0, ld, dt, dlnA, h_io,
+                                                  T1, Y1, cell_status, n_acc, n_rej, grid, st);
+        else
+            e = scdev::launch_integrate_static(plan->np, plan->dm, o, plan->opt.method, n, T0, p, Y0, ld, dt, dlnA,
+                                               h_io, T1, Y1, cell_status, n_acc, n_rej, grid, st);
+    } else if (plan->sparse) {
+        e = scdev::launch_integrate_sp(plan->vpl, plan->dm, plan->ds, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1,
+                                       cell_status, n_acc, n_rej, st);
     } else {
         e = scdev::launch_integrate(plan->np, plan->dm, o, plan->opt.method, n, T0, p, Y0, ld, dt, dlnA, h_io, T1,
                                     Y1, cell_status, n_acc, n_rej, st);
     }
     return e == hipSuccess ? SC_OK : hip_fail(e, "integrate launch");
+}
+
+sc_status sc_integrate(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0, int64_t ld,
+                       const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
+                       int32_t *cell_status, int32_t *n_acc, int32_t *n_rej, void *stream)
+{
+    return integrate_impl(plan, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, cell_status, n_acc, n_rej, stream, false);
+}
+
+sc_status sc_integrate_noalloc(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0,
+                               int64_t ld, const double *dt, const double *dlnA, double *h_io, double *T1,
+                               double *Y1, int32_t *cell_status, int32_t *n_acc, int32_t *n_rej, void *stream)
+{
+    return integrate_impl(plan, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, cell_status, n_acc, n_rej, stream, true);
 }
 
 sc_status sc_vjp(sc_plan *plan, int64_t n, const double *T, const double *p, const double *Y, int64_t ld,
@@ -396,6 +578,8 @@ sc_status sc_vjp(sc_plan *plan, int64_t n, const double *T, const double *p, con
     sc_status s = check_common(plan, n, ld, {T, p, Y, wT, wY, gT, gY});
     if (s != SC_OK) return s;
     if (plan->dm.cv) return fail(SC_EUNSUPPORTED, "the VJP supports the constant-pressure reactor only");
+    if (plan->m.N + 1 > sc::MAX_STATE)
+        return fail(SC_EUNSUPPORTED, "the VJP supports up to " + std::to_string(sc::MAX_STATE - 1) + " species");
     if (n == 0) return SC_OK;
     DeviceGuard g(plan->device);
     hipError_t e = scdev::launch_vjp(plan->np, plan->dm, n, T, p, Y, ld, dlnA, wT, wY, gT, gY, g_dlnA_cell,
@@ -425,6 +609,8 @@ sc_status sc_adjoint(sc_plan *plan, int64_t n, const double *T0, const double *p
     if (plan->dm.cv) return fail(SC_EUNSUPPORTED, "the adjoint supports the constant-pressure reactor only");
     if (plan->opt.method != SC_METHOD_ROS4)
         return fail(SC_EUNSUPPORTED, "the adjoint supports the Rosenbrock method only");
+    if (plan->m.N + 1 > sc::MAX_STATE)
+        return fail(SC_EUNSUPPORTED, "the adjoint supports up to " + std::to_string(sc::MAX_STATE - 1) + " species");
     const int R = plan->dm.R;
     hipStream_t st = (hipStream_t)stream;
     DeviceGuard g(plan->device);

@@ -46,6 +46,22 @@ struct DevMech {
     __host__ __device__ const double *nasa() const { return sp + 2 * N; }  // [c*N + k]
 };
 
+// The sparse kernels' view of a mechanism's compiled sparse algebra (device
+// pointers) and their per-cell LDS layout (offsets in doubles; NV = 64 VPL
+// doubles per state vector).
+struct DevSparse {
+    int n, nnz, nl_lu, nl_fw, nl_bw, n_u;
+    int E, C, G, H, WD, UA, U, X, DINV, size;
+    int NV;
+    const int *lu_b_lvl, *lu_c_lvl, *fw_lvl, *bw_lvl;
+    const uint32_t *lu_b, *lu_u, *diag;
+    const uint64_t *lu_c, *fw, *bw;
+    const uint16_t *rxi;   // [R][RXI_SIZE], reaction execution order
+    const int32_t *comp;   // per species k: pos, e_kk, e_kT, e_kS, e_Tk, e_Sk; then pos_T, e_TT, e_SS
+    const uint16_t *emap;  // n * n: (row, column) position -> entry or NOENT
+};
+constexpr int CMP = 6;  // comp entries per species
+
 struct Opts {
     double rtol, atol;
     double hmax_frac;  // > 0: steps capped at hmax_frac * dt
@@ -75,8 +91,40 @@ hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int 
                                    int32_t *na, int32_t *nr, int grid, hipStream_t s);
 hipError_t order_cells(int order, int64_t n, const double *dt, const int32_t *na, const int32_t *nr,
                        void **ws, size_t *ws_bytes, int32_t **perm, hipStream_t s);
+hipError_t order_ws_need(int order, int64_t n, size_t *need, hipStream_t s);
+hipError_t order_cells_in(int order, int64_t n, const double *dt, const int32_t *na, const int32_t *nr, void *ws,
+                          size_t ws_bytes, int32_t **perm, hipStream_t s);
+// device address, size and cell limit of the allocation-free entry point's
+// fixed scratch on `device` (which must be current)
+hipError_t noalloc_scratch(int device, void **ptr, size_t *bytes, int64_t *max_cells);
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
 int persistent_capacity(int np, int device);
+
+// sparse linear algebra kernels (sparse.hip); vpl = state components per lane
+hipError_t launch_rhs_sp(int vpl, const DevMech &m, const DevSparse &sp, int64_t n, const double *T,
+                         const double *p, const double *Y, int64_t ld, const double *dlnA, double *fT, double *fY,
+                         hipStream_t s);
+hipError_t launch_jac_sp(int vpl, const DevMech &m, const DevSparse &sp, int64_t n, const double *T,
+                         const double *p, const double *Y, int64_t ld, const double *dlnA, double *J,
+                         hipStream_t s);
+hipError_t launch_linsolve_sp(int vpl, const DevMech &m, const DevSparse &sp, int64_t n, const double *T,
+                              const double *p, const double *Y, int64_t ld, const double *dlnA, const double *hg,
+                              const double *b, double *x, hipStream_t s);
+hipError_t launch_integrate_sp(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o, int64_t n,
+                               const double *T0, const double *p, const double *Y0, int64_t ld, const double *dt,
+                               const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na,
+                               int32_t *nr, hipStream_t s);
+hipError_t launch_integrate_sp_persistent(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o,
+                                          int64_t n, const double *T0, const double *p, const double *Y0,
+                                          int64_t ld, const double *dt, const double *dlnA, double *h_io,
+                                          double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr,
+                                          unsigned long long *queue, const int32_t *perm, int tile, int grid,
+                                          hipStream_t s);
+hipError_t launch_integrate_sp_static(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o, int64_t n,
+                                      const double *T0, const double *p, const double *Y0, int64_t ld,
+                                      const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
+                                      int32_t *st, int32_t *na, int32_t *nr, int grid, hipStream_t s);
+int persistent_capacity_sp(int vpl, const DevSparse &sp, int device);
 
 // adjoint (adjoint.hip)
 hipError_t launch_vjp(int np, const DevMech &m, int64_t n, const double *T, const double *p, const double *Y,

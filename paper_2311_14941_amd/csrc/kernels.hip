@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include <hipcub/hipcub.hpp>
 
@@ -281,12 +282,15 @@ hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int 
 
 // Cell permutation for the persistent queue: indices sorted by descending
 // key (dt, or the previous call's step count), by a device radix sort.
-// `ws` is grown on demand: [perm_in | perm_out | keys_out | cost keys | temp].
-hipError_t order_cells(int order, int64_t n, const double *dt, const int32_t *na, const int32_t *nr,
-                       void **ws, size_t *ws_bytes, int32_t **perm, hipStream_t s)
+// Workspace layout: [perm_in | perm_out | keys_out | cost keys | temp].
+namespace {
+size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+// Workspace bytes the ordering of n cells needs (a size query of the sort:
+// no allocation, no launch).
+hipError_t order_ws_need(int order, int64_t n, size_t *need, hipStream_t s)
 {
-    const size_t al = 256;
-    auto up = [&](size_t b) { return (b + al - 1) / al * al; };
     size_t tmp = 0;
     hipError_t e;
     if (order == SC_ORDER_DT)
@@ -298,16 +302,22 @@ hipError_t order_cells(int order, int64_t n, const double *dt, const int32_t *na
                                                          (const int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 32,
                                                          s);
     if (e != hipSuccess) return e;
-    const size_t b_perm = up(sizeof(int32_t) * n), b_keys = up(sizeof(double) * n);
-    const size_t need = 2 * b_perm + 2 * b_keys + up(tmp);
-    if (*ws_bytes < need) {
-        if (*ws) (void)hipFree(*ws);
-        *ws = nullptr;
-        *ws_bytes = 0;
-        if ((e = hipMalloc(ws, need)) != hipSuccess) return e;
-        *ws_bytes = need;
-    }
-    char *base = (char *)*ws;
+    *need = 2 * up256(sizeof(int32_t) * n) + 2 * up256(sizeof(double) * n) + up256(tmp);
+    return hipSuccess;
+}
+
+// The ordering in a workspace the caller provides (at least order_ws_need
+// bytes, 256-byte aligned); allocates nothing.
+hipError_t order_cells_in(int order, int64_t n, const double *dt, const int32_t *na, const int32_t *nr, void *ws,
+                          size_t ws_bytes, int32_t **perm, hipStream_t s)
+{
+    size_t need = 0;
+    hipError_t e = order_ws_need(order, n, &need, s);
+    if (e != hipSuccess) return e;
+    if (ws_bytes < need) return hipErrorInvalidValue;
+    const size_t b_perm = up256(sizeof(int32_t) * n), b_keys = up256(sizeof(double) * n);
+    size_t tmp = need - 2 * b_perm - 2 * b_keys;
+    char *base = (char *)ws;
     int32_t *pin = (int32_t *)base, *pout = (int32_t *)(base + b_perm);
     void *kout = base + 2 * b_perm, *kcost = base + 2 * b_perm + b_keys, *temp = base + 2 * b_perm + 2 * b_keys;
     const unsigned blocks = (unsigned)((n + 255) / 256);
@@ -321,6 +331,59 @@ hipError_t order_cells(int order, int64_t n, const double *dt, const int32_t *na
     }
     *perm = pout;
     return e != hipSuccess ? e : hipGetLastError();
+}
+
+// The ordering in a plan-owned workspace `ws`, grown on demand.
+hipError_t order_cells(int order, int64_t n, const double *dt, const int32_t *na, const int32_t *nr,
+                       void **ws, size_t *ws_bytes, int32_t **perm, hipStream_t s)
+{
+    size_t need = 0;
+    hipError_t e = order_ws_need(order, n, &need, s);
+    if (e != hipSuccess) return e;
+    if (*ws_bytes < need) {
+        if (*ws) (void)hipFree(*ws);
+        *ws = nullptr;
+        *ws_bytes = 0;
+        if ((e = hipMalloc(ws, need)) != hipSuccess) return e;
+        *ws_bytes = need;
+    }
+    return order_cells_in(order, n, dt, na, nr, *ws, *ws_bytes, perm, s);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free integration entry point: the
+// queue counter (first 256 bytes) and the cell-ordering workspace.  One copy
+// per device, held until the process ends; every call on a device shares it
+// (concurrent calls on one device race).  Host code reaches it only through
+// the address hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+constexpr int64_t NOALLOC_MAX_CELLS = 262144;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+// Resolve (once per device, with that device current) the device address of
+// the scratch array.
+hipError_t noalloc_scratch(int device, void **ptr, size_t *bytes, int64_t *max_cells)
+{
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    *bytes = NOALLOC_SCRATCH_BYTES;
+    *max_cells = NOALLOC_MAX_CELLS;
+    return hipSuccess;
 }
 
 // clears the queue counter with a kernel (safe inside captured graphs)

@@ -213,9 +213,9 @@ void validate(Mech &m)
         if (r.kind == RX_TROE && r.troe[3] == 0 && r.troe[4] <= 0)
             throw ParseError("bad Troe parameters");
     }
-    if (m.N + 1 > MAX_STATE)
+    if (m.N + 1 > MAX_STATE_SPARSE)
         throw Unsupported("mechanism has " + std::to_string(m.N) + " species; the kernels support up to " +
-                          std::to_string(MAX_STATE - 1));
+                          std::to_string(MAX_STATE_SPARSE - 1));
 }
 
 void build_tables(Mech &m)
@@ -313,11 +313,11 @@ void count_work(Mech &m)
     Counts &c = m.cnt;
     // structural pattern of the sparse analytical terms (species block, T
     // row and column); the rank-one density coupling makes J itself dense
-    m.pattern.assign((size_t)n * n, 0);
+    std::vector<uint8_t> pat((size_t)n * n, 0);
     for (int i = 0; i < n; ++i) {
-        m.pattern[i * n + i] = 1;
-        m.pattern[i * n + N] = 1;
-        m.pattern[N * n + i] = 1;
+        pat[i * n + i] = 1;
+        pat[i * n + N] = 1;
+        pat[N * n + i] = 1;
     }
     int64_t f_rx = 0, f_jrx = 0;
     int exps = 1;  // log T
@@ -330,7 +330,7 @@ void count_work(Mech &m)
             for (auto &x : r.eff)
                 if (x.second != 1.0) deps.push_back(x.first);
         for (int a : rows)
-            for (int b : deps) m.pattern[a * n + b] = 1;
+            for (int b : deps) pat[a * n + b] = 1;
         const int ns = (int)(r.reac.size() + r.prod.size());
         int nu_tot = 0;
         for (auto &x : r.reac) nu_tot += x.second;
@@ -351,13 +351,14 @@ void count_work(Mech &m)
         if (r.kind == RX_TROE) f_jrx += 40;
     }
     int nnz = 0;
-    for (auto v : m.pattern) nnz += v;
+    for (auto v : pat) nnz += v;
     c.nnz_jac = nnz;
     c.nnz_lu = n * n;
     c.exp_per_rhs = exps;
     const int64_t f_thermo = 31 * (int64_t)N, f_mix = 8 * (int64_t)N, f_fin = 6 * (int64_t)N + 4;
     c.flops_rhs = f_thermo + f_mix + f_rx + f_fin;
-    c.flops_jac = c.flops_rhs + f_jrx + 6 * (int64_t)n * n + 10 * (int64_t)N;
+    c.flops_jac_terms = f_jrx + 10 * (int64_t)N;
+    c.flops_jac = c.flops_rhs + c.flops_jac_terms + 6 * (int64_t)n * n;
     int64_t lu = 0;
     for (int k = 0; k < n; ++k) lu += (n - k - 1) + 2LL * (n - k - 1) * (n - k - 1);
     c.flops_lu = lu;
@@ -378,8 +379,11 @@ Mech load_mechanism(const std::string &text)
     validate(m);
     build_tables(m);
     count_work(m);
+    compile_sparse(m);
     const int n = m.N + 1;
-    m.n_padded = n <= 16 ? 16 : n <= 32 ? 32 : n <= 56 ? 56 : 64;
+    // register rows per cell of the dense kernels; above 64 only the sparse
+    // kernels (two state components per lane) apply
+    m.n_padded = n <= 16 ? 16 : n <= 32 ? 32 : n <= 56 ? 56 : n <= 64 ? 64 : 128;
     return m;
 }
 

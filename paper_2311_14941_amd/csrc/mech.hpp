@@ -19,7 +19,61 @@ namespace sc {
 constexpr int MAXSIDE = 3;                  // distinct species per reaction side
 constexpr int MAXENH = 4;                   // enhanced third-body species per reaction
 constexpr int NDEP = 2 * MAXSIDE + MAXENH;  // dependency slots per reaction
-constexpr int MAX_STATE = 64;               // N + 1 supported by the one-wave kernels
+constexpr int MAX_STATE = 64;               // N + 1 supported by the dense one-wave kernels
+constexpr int MAX_STATE_SPARSE = 128;       // N + 1 supported by the sparse kernels (two components per lane)
+// per-reaction entry indices of the sparse kernels: for each row slot (3
+// reactants, 3 products) the entries of its dependency slots and of the
+// temperature column, then the temperature row's entries of the dependency
+// slots (unused slots hold NOENT)
+constexpr int RXI_ROW = NDEP + 1;
+constexpr int RXI_TROW = 2 * MAXSIDE * RXI_ROW;
+constexpr int RXI_SIZE = RXI_TROW + NDEP + 2;  // 80 (a 160-byte record)
+constexpr uint16_t NOENT = 0xffff;
+
+// The sparse linear algebra of one mechanism (paper Sec. 2.5: the sparse
+// analytical Jacobian and the sparse algebra management of the mechanism).
+// The iteration matrix M = I/(h gamma) - J is solved through a bordered
+// system of order n = N + 2 in the scaled unknowns z_k = x_k / W_k, x_T and
+// sigma = (sum_m v_m x_m), in which the species block holds only the terms
+// P_km = sum_j nu_kj dq_j/dC_m (fixed sparsity from the reaction list, with
+// the third-body concentration rewritten so only enhanced species appear),
+// and the dense couplings are two border rows and columns (temperature and
+// the density term of constant pressure, or the total concentration of
+// constant volume).  The species block is put in minimum-degree order, the
+// borders last, so no fill enters the species block from them.  The
+// symbolic LU (right-looking, no pivoting) fixes the L+U pattern; the
+// numeric work is a static schedule in levels of independent operations.
+struct SparseLU {
+    int n = 0, nnz = 0;
+    std::vector<int> perm;        // position -> variable (species 0..N-1, N = T, N + 1 = sigma)
+    std::vector<int> pos;         // variable -> position
+    std::vector<int> erow, ecol;  // entry -> (row position, column position), row-major order
+    std::vector<int> emap;        // n * n: (row position, column position) -> entry or -1
+    std::vector<uint8_t> apat;    // n * n: structural pattern of the bordered matrix (before fill)
+    // LU, level by level: scale the L entries of the level's pivots
+    // (b items: e_ik | e_kk << 16), then the Schur updates (c items:
+    // e_ij | e_ik << 16 | e_kj << 32) whose targets may repeat within a level
+    std::vector<int> lu_b_lvl, lu_c_lvl;  // level offsets into b / c items (size levels + 1)
+    std::vector<uint32_t> lu_b;
+    std::vector<uint64_t> lu_c;
+    std::vector<uint32_t> lu_u;           // strict U entries with their pivot: e_kj | k << 16 (row scaling)
+    std::vector<uint32_t> diag;           // diagonal entry of each position
+    // triangular solves (unit L, then the row-scaled unit U): items
+    // i | p << 16 | e << 32 meaning x_i -= value(e) x_p, level by level
+    std::vector<int> fw_lvl, bw_lvl;
+    std::vector<uint64_t> fw, bw;
+    // transposed solves (U'^T, then L^T) for the adjoint
+    std::vector<int> tfw_lvl, tbw_lvl;
+    std::vector<uint64_t> tfw, tbw;
+    std::vector<uint16_t> rxi;            // [R][RXI_SIZE] entry indices per reaction, original order
+    // entries each state component writes when the matrix is formed: per
+    // species k: diagonal, T column, sigma column, T row, sigma row; for T:
+    // (T,T), (sigma,sigma), (T,sigma), (sigma,T) (the last two may be absent)
+    std::vector<int> e_kk, e_kT, e_kS, e_Tk, e_Sk;
+    int e_TT = -1, e_SS = -1, e_TS = -1, e_ST = -1;
+    int64_t nnz_a = 0, updates = 0;       // bordered matrix before fill; Schur updates
+    int64_t flops_lu = 0, flops_solve = 0;
+};
 
 enum RxKind { RX_PLAIN = 0, RX_THIRD = 1, RX_TROE = 2 };
 
@@ -56,6 +110,7 @@ struct Counts {
     int exp_per_rhs = 0;
     int64_t flops_rhs = 0, flops_jac = 0, flops_lu = 0, flops_solve = 0, flops_step = 0;
     int64_t flops_attempt = 0, flops_accept = 0;
+    int64_t flops_jac_terms = 0;  // the Jacobian pass beyond its right-hand side (reaction derivative terms)
 };
 
 struct Mech {
@@ -70,13 +125,19 @@ struct Mech {
     int n_third = 0, n_troe = 0;
     int n_padded = 0;
     Tables tab;
-    Counts cnt;
-    std::vector<uint8_t> pattern;  // (N+1)^2 structural pattern of the sparse Jacobian terms
+    Counts cnt;         // the dense kernels' work
+    Counts cnt_sparse;  // the sparse kernels' work (LU and solves from the schedule)
+    std::vector<uint8_t> pattern;  // N^2 structural pattern of the species terms P_km (with the diagonal)
+    SparseLU sp;
 
     int species(const std::string &s) const;
 };
 
 // Parse + validate + compile.  Throws ParseError or Unsupported.
 Mech load_mechanism(const std::string &text);
+
+// The sparse compile (sparse.cpp): ordering, symbolic LU, schedules, entry
+// indices and counts of a parsed, validated mechanism.
+void compile_sparse(Mech &m);
 
 }  // namespace sc

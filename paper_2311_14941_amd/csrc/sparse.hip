@@ -1,0 +1,757 @@
+// Kernels with the sparse linear algebra (gfx950): one 64-lane wavefront per
+// cell, as in the dense kernels, but the iteration matrix lives in LDS as the
+// L+U entries of the bordered system the mechanism compiler built (sparse.cpp)
+// and is factorised and solved by following that compiler's static level
+// schedules.  State vectors hold VPL components per lane (component
+// c = lane + 64 v), so mechanisms of up to 127 species fit one wave.
+//
+// The bordered system (order N + 2, unknowns z_k = x_k / W_k, x_T, sigma):
+//   row k:     z_k/hg - sum_m P_km z_m - us_k sigma - (P_kT/rho + ct us_k) x_T = b_k / W_k
+//   row T:     sum_m A_Tm z_m + A_TT x_T = b_T
+//   row sigma: vs sum_m z_m - sigma = 0
+// with P_km = sum_j nu_kj dq_j/dC_m (the sparse analytical terms, scattered
+// reaction by reaction), us_k = UA_k/rho, vs = Wbar, ct = 1/T at constant
+// pressure (the density border) and us_k = UA_k, vs = 1, ct = 0 at constant
+// volume (the total-concentration border); UA_k = sum_j nu_kj e_j with e_j
+// the reaction's Euler remainder (constant pressure) or dq_j/d[M] (constant
+// volume).  Eliminating sigma gives back M = I/hg - J exactly (paper
+// Sec. 2.5: sparse analytical Jacobian, sparse algebra management).
+//
+// Every schedule phase is a list of independent items processed 64 at a
+// time, four groups in flight; items of one phase that update the same entry
+// use LDS atomics, so one wave's results do not depend on anything but the
+// schedule (bitwise equal across launch modes).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "core.hpp"
+
+namespace scdev {
+
+
+// ---------------------------------------------------------------------------
+// helpers over VPL components per lane
+// ---------------------------------------------------------------------------
+template <int VPL>
+__device__ __forceinline__ double vsum(const double (&a)[VPL])
+{
+    double s = a[0];
+#pragma unroll
+    for (int v = 1; v < VPL; ++v) s += a[v];
+    return wave_sum(s);
+}
+
+// the temperature component (c = N) sits in slot VPL - 1 (VPL is the least
+// number of slots that holds N + 1 components)
+template <int VPL>
+__device__ __forceinline__ double comp_T(const DevMech &m, const double (&y)[VPL])
+{
+    return rdlane(y[VPL - 1], m.N - 64 * (VPL - 1));
+}
+
+template <int VPL>
+__device__ __forceinline__ void load_state_v(const DevMech &m, const double *T, const double *Y, int64_t ld,
+                                             int64_t cell, int lane, double (&y)[VPL])
+{
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int c = lane + 64 * v;
+        y[v] = c < m.N ? Y[(int64_t)c * ld + cell] : c == m.N ? T[cell] : 0.0;
+    }
+}
+
+template <int VPL>
+__device__ __forceinline__ void store_state_v(const DevMech &m, double *T, double *Y, int64_t ld, int64_t cell,
+                                              int lane, const double (&y)[VPL])
+{
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int c = lane + 64 * v;
+        if (c < m.N) Y[(int64_t)c * ld + cell] = y[v];
+        if (c == m.N) T[cell] = y[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// thermodynamics, right-hand side and Jacobian terms
+// ---------------------------------------------------------------------------
+// Mixture state from y; writes C, g/RT, h/RT and clears the accumulators.
+template <int VPL>
+__device__ __forceinline__ Mix<> mixture_v(const DevMech &m, const DevSparse &sp, double *lds,
+                                           const double (&y)[VPL], double p, Thermo<> (&th)[VPL], int lane)
+{
+    const int N = m.N;
+    Mix<> x;
+    x.T = comp_T<VPL>(m, y);
+    x.invT = 1.0 / x.T;
+    x.lnT = log(x.T);
+    x.p = p;
+    double yw[VPL], cpw[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int c = lane + 64 * v;
+        th[v] = Thermo<>{0.0, 0.0, 0.0, 0.0};
+        yw[v] = cpw[v] = 0.0;
+        if (c < N) {
+            th[v] = nasa7<double>(m, c, x.T, x.lnT, x.invT);
+            yw[v] = y[v] * m.invW()[c];
+            cpw[v] = th[v].cpR * yw[v];
+        }
+    }
+    x.Wbar = 1.0 / vsum<VPL>(yw);
+    x.cp = m.Rgas * vsum<VPL>(cpw);
+    if (m.cv) {
+        x.rho = p;
+        x.p = p * m.Rgas * x.T / x.Wbar;
+        x.cp = x.cp - m.Rgas / x.Wbar;
+    } else {
+        x.rho = p * x.Wbar * x.invT / m.Rgas;
+    }
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int c = lane + 64 * v;
+        if (c < N) {
+            lds[sp.C + c] = x.rho * yw[v];
+            lds[sp.G + c] = th[v].hRT - th[v].sR;
+            lds[sp.H + c] = th[v].hRT;
+            lds[sp.WD + c] = 0.0;
+        }
+        if (c <= N) lds[sp.UA + c] = 0.0;
+    }
+    return x;
+}
+
+// f(y): dY_k/dt and dT/dt, VPL components per lane (0 beyond N).
+template <int VPL>
+__device__ void rhs_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&y)[VPL], double p,
+                      const double *dlnA, int lane, double (&f)[VPL])
+{
+    const int N = m.N, R = m.R;
+    Thermo<> th[VPL];
+    const Mix<> x = mixture_v<VPL>(m, sp, lds, y, p, th, lane);
+    __syncthreads();
+#pragma unroll 1
+    for (int j = lane; j < R; j += WAVE) {
+        const RxRec rr = load_rec(m, j);
+        const double dl = dlnA ? dlnA[rr.orig] : 0.0;
+        const RxOut<> o = reaction<false>(m, lds, rr, x, dl, sp.C, sp.G, sp.H);
+#pragma unroll
+        for (int i = 0; i < sc::MAXSIDE; ++i) {
+            if (i < rr.nr) atomicAdd(&lds[sp.WD + rr.rsp[i]], -(double)rr.rnu[i] * o.q);
+            if (i < rr.np) atomicAdd(&lds[sp.WD + rr.psp[i]], (double)rr.pnu[i] * o.q);
+        }
+    }
+    __syncthreads();
+    double hw[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int c = lane + 64 * v;
+        f[v] = hw[v] = 0.0;
+        if (c < N) {
+            const double wd = lds[sp.WD + c];
+            f[v] = m.W()[c] * wd / x.rho;
+            hw[v] = (m.cv ? th[v].hRT - 1.0 : th[v].hRT) * wd;
+        }
+    }
+    const double fT = -m.Rgas * x.T * vsum<VPL>(hw) / (x.rho * x.cp);
+#pragma unroll
+    for (int v = 0; v < VPL; ++v)
+        if (lane + 64 * v == N) f[v] = fT;
+    __syncthreads();
+}
+
+// Jacobian pass: f(y), and the bordered matrix of I/hg - J formed in the L+U
+// entries (fill entries zero).  The reaction loop scatters -nu dq/dC and
+// -nu dq/dT into the species rows and the reaction-enthalpy-weighted
+// derivatives into the temperature row; the border entries are finished per
+// state component after one barrier.
+template <int VPL>
+__device__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&y)[VPL], double p,
+                      const double *dlnA, int lane, double inv_hg, double (&f)[VPL])
+{
+    const int N = m.N, R = m.R;
+    double *E = lds + sp.E;
+    Thermo<> th[VPL];
+    const Mix<> x = mixture_v<VPL>(m, sp, lds, y, p, th, lane);
+#pragma unroll 4
+    for (int e = lane; e < sp.nnz; e += WAVE) E[e] = 0.0;
+    __syncthreads();
+    const double RT = m.Rgas * x.T;
+#pragma unroll 1
+    for (int j = lane; j < R; j += WAVE) {
+        const RxRec rr = load_rec(m, j);
+        uint16_t ix[sc::RXI_SIZE];
+        __builtin_memcpy(ix, sp.rxi + (size_t)j * sc::RXI_SIZE, sizeof ix);
+        const double dl = dlnA ? dlnA[rr.orig] : 0.0;
+        const RxOut<> o = reaction<true>(m, lds, rr, x, dl, sp.C, sp.G, sp.H);
+        // temperature-row weight: the reaction enthalpy (constant pressure) or
+        // internal energy (constant volume), per unit of progress
+        const double dHJ = m.cv ? (o.dH - rr.dnu) * RT : o.dH * RT;
+        bool use[sc::NDEP];
+#pragma unroll
+        for (int i = 0; i < sc::MAXSIDE; ++i) {
+            use[i] = i < rr.nr;
+            use[3 + i] = i < rr.np;
+        }
+#pragma unroll
+        for (int e = 0; e < sc::MAXENH; ++e) use[6 + e] = e < rr.neff;
+#pragma unroll
+        for (int r = 0; r < 2 * sc::MAXSIDE; ++r) {
+            const bool isr = r < sc::MAXSIDE;
+            const int ri = isr ? r : r - sc::MAXSIDE;
+            if (ri >= (isr ? rr.nr : rr.np)) continue;
+            const int row = isr ? rr.rsp[ri] : rr.psp[ri];
+            const double nu = isr ? -(double)rr.rnu[ri] : (double)rr.pnu[ri];
+            atomicAdd(&lds[sp.WD + row], nu * o.q);
+            atomicAdd(&lds[sp.UA + row], nu * o.euler);
+#pragma unroll
+            for (int s = 0; s < sc::NDEP; ++s)
+                if (use[s]) atomicAdd(&E[ix[r * sc::RXI_ROW + s]], -nu * o.d[s]);
+            atomicAdd(&E[ix[r * sc::RXI_ROW + sc::NDEP]], -nu * o.dT);
+        }
+#pragma unroll
+        for (int s = 0; s < sc::NDEP; ++s)
+            if (use[s]) atomicAdd(&E[ix[sc::RXI_TROW + s]], dHJ * o.d[s]);
+        atomicAdd(&E[ix[sc::RXI_TROW + sc::NDEP]], dHJ * o.dT);
+        if (m.cv) atomicAdd(&lds[sp.UA + N], dHJ * o.euler);
+    }
+    __syncthreads();
+    const double one = m.cv ? 1.0 : 0.0;
+    double hw[VPL], eu[VPL], cpf[VPL], dcp[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int c = lane + 64 * v;
+        f[v] = hw[v] = eu[v] = cpf[v] = dcp[v] = 0.0;
+        if (c < N) {
+            const double Wk = m.W()[c], iw = m.invW()[c];
+            const double wd = lds[sp.WD + c], ua = lds[sp.UA + c];
+            f[v] = Wk * wd / x.rho;
+            hw[v] = (th[v].hRT - one) * wd;
+            eu[v] = th[v].hRT * ua / x.rho;      // (h_k/(R T W_k)) u_k, u_k = W_k UA_k / rho
+            cpf[v] = (th[v].cpR - one) * f[v] * iw;
+            dcp[v] = th[v].dcpR * y[v] * iw;
+        }
+    }
+    const double H = RT * vsum<VPL>(hw);
+    const double Eu = m.cv ? 0.0 : RT * vsum<VPL>(eu);
+    const double Scpf = m.Rgas * vsum<VPL>(cpf);
+    const double Sdcp = m.Rgas * vsum<VPL>(dcp);
+    const double fT = -H / (x.rho * x.cp);
+    const double vs = m.cv ? 1.0 : x.Wbar;
+    const double ct = m.cv ? 0.0 : x.invT;
+    const double tb = m.cv ? lds[sp.UA + N] : x.Wbar * Eu;
+    const double icp = 1.0 / x.cp;
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int c = lane + 64 * v;
+        if (c < N) {
+            const int32_t *cm = sp.comp + CMP * c;
+            const double us = m.cv ? lds[sp.UA + c] : lds[sp.UA + c] / x.rho;
+            E[cm[1]] += inv_hg;
+            E[cm[2]] = E[cm[2]] / x.rho - ct * us;
+            E[cm[3]] = -us;
+            E[cm[4]] = (E[cm[4]] + tb + fT * m.Rgas * (th[v].cpR - one)) * icp;
+            E[cm[5]] = vs;
+        } else if (c == N) {
+            f[v] = fT;
+            const int32_t *cm = sp.comp + CMP * N;
+            const double eT = m.cv ? 0.0 : Eu * x.invT;
+            E[cm[1]] = inv_hg + (E[cm[1]] / x.rho + eT + Scpf + fT * Sdcp) * icp;
+            E[cm[2]] = -1.0;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// schedules
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lo16(uint64_t x) { return (int)(x & 0xffff); }
+__device__ __forceinline__ int mid16(uint64_t x) { return (int)((x >> 16) & 0xffff); }
+__device__ __forceinline__ int hi16(uint64_t x) { return (int)((x >> 32) & 0xffff); }
+
+// Items [q0, q1) of an update phase: target -= value(a) * value(b), with the
+// target/a/b LDS indices taken from each item by TA/TB/TC (entries or vector
+// positions), four 64-item groups in flight.
+template <class F>
+__device__ __forceinline__ void run_items(const uint64_t *items, int q0, int q1, int lane, F op)
+{
+#pragma unroll 1
+    for (int base = q0; base < q1; base += 4 * WAVE) {  // uniform trip count across the wave
+        uint64_t it[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = base + u * WAVE + lane;
+            ok[u] = q < q1;
+            it[u] = ok[u] ? items[q] : 0;
+        }
+        op(it, ok);
+    }
+}
+
+// Numeric LU of the formed matrix in E by the static level schedule, then
+// dinv = 1/u_kk and the rows of U scaled to a unit diagonal.
+__device__ void lu_v(const DevSparse &sp, double *lds, int lane)
+{
+    double *E = lds + sp.E;
+    double *DINV = lds + sp.DINV;
+#pragma unroll 1
+    for (int l = 0; l < sp.nl_lu; ++l) {
+        const int b0 = sp.lu_b_lvl[l], b1 = sp.lu_b_lvl[l + 1];
+#pragma unroll 1
+        for (int q = b0 + lane; q < b1; q += WAVE) {
+            const uint32_t it = sp.lu_b[q];
+            const int eik = (int)(it & 0xffff), ekk = (int)(it >> 16);
+            E[eik] = E[eik] / E[ekk];
+        }
+        __syncthreads();
+        const int c0 = sp.lu_c_lvl[l], c1 = sp.lu_c_lvl[l + 1];
+        if (c1 > c0) {
+            run_items(sp.lu_c, c0, c1, lane, [&](const uint64_t (&it)[4], const bool (&ok)[4]) {
+                double a[4], b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = ok[u] ? E[mid16(it[u])] : 0.0;
+                    b[u] = ok[u] ? E[hi16(it[u])] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (ok[u]) atomicAdd(&E[lo16(it[u])], -a[u] * b[u]);
+            });
+            __syncthreads();
+        }
+    }
+#pragma unroll 1
+    for (int k = lane; k < sp.n; k += WAVE) DINV[k] = 1.0 / E[sp.diag[k]];
+    __syncthreads();
+#pragma unroll 2
+    for (int q = lane; q < sp.n_u; q += WAVE) {
+        const uint32_t it = sp.lu_u[q];
+        E[it & 0xffff] *= DINV[it >> 16];
+    }
+    __syncthreads();
+}
+
+// one sweep of a triangular solve: x_i -= E[e] x_p, level by level
+__device__ __forceinline__ void sweep(const double *E, double *X, const int *lvl, const uint64_t *items, int nl,
+                                      int lane)
+{
+#pragma unroll 1
+    for (int l = 0; l < nl; ++l) {
+        run_items(items, lvl[l], lvl[l + 1], lane, [&](const uint64_t (&it)[4], const bool (&ok)[4]) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = ok[u] ? E[hi16(it[u])] : 0.0;
+                b[u] = ok[u] ? X[mid16(it[u])] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (ok[u]) atomicAdd(&X[lo16(it[u])], -a[u] * b[u]);
+        });
+        __syncthreads();
+    }
+}
+
+// Solve M x = b with the factors in E (b, x: VPL components per lane).
+template <int VPL>
+__device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&b)[VPL], int lane,
+                        double (&x)[VPL])
+{
+    const int N = m.N;
+    const double *E = lds + sp.E;
+    double *X = lds + sp.X;
+    const double *DINV = lds + sp.DINV;
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int c = lane + 64 * v;
+        if (c < N) X[sp.comp[CMP * c]] = b[v] * m.invW()[c];
+        if (c == N) X[sp.comp[CMP * N]] = b[v];
+    }
+    if (lane == 0) X[sp.n - 1] = 0.0;  // sigma row
+    __syncthreads();
+    sweep(E, X, sp.fw_lvl, sp.fw, sp.nl_fw, lane);
+#pragma unroll 1
+    for (int k = lane; k < sp.n; k += WAVE) X[k] *= DINV[k];
+    __syncthreads();
+    sweep(E, X, sp.bw_lvl, sp.bw, sp.nl_bw, lane);
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int c = lane + 64 * v;
+        x[v] = c < N ? X[sp.comp[CMP * c]] * m.W()[c] : c == N ? X[sp.comp[CMP * N]] : 0.0;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// one Rosenbrock attempt and the integration of a cell
+// ---------------------------------------------------------------------------
+template <int VPL>
+__device__ void ros_attempt_v(const DevMech &m, const DevSparse &sp, const Opts &o, double *lds,
+                              const double (&y)[VPL], double p, const double *dlnA, int lane, double hc, double *err,
+                              double (&ynew)[VPL])
+{
+    const int n = m.N + 1;
+    double *U = lds + sp.U;
+    const int NV = sp.NV;
+    double f0[VPL], flast[VPL];
+    jac_v<VPL>(m, sp, lds, y, p, dlnA, lane, 1.0 / (GAM * hc), f0);
+    lu_v(sp, lds, lane);
+    const double ih = 1.0 / hc;
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) flast[v] = f0[v];
+#pragma unroll 1
+    for (int i = 0; i < NS; ++i) {
+        double fi[VPL];
+        const int reuse = TREUSE[i];
+        if (reuse == 0) {
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) fi[v] = f0[v];
+        } else if (reuse > 0) {
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) fi[v] = flast[v];
+        } else {
+            double ys[VPL];
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+                ys[v] = y[v];
+                for (int j = 0; j < i; ++j) ys[v] += TA[i][j] * U[j * NV + lane + 64 * v];
+            }
+            rhs_v<VPL>(m, sp, lds, ys, p, dlnA, lane, fi);
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) flast[v] = fi[v];
+        }
+        double ui[VPL];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+            for (int j = 0; j < i; ++j) fi[v] += (TC[i][j] * ih) * U[j * NV + lane + 64 * v];
+            if (lane + 64 * v >= n) fi[v] = 0.0;
+        }
+        solve_v<VPL>(m, sp, lds, fi, lane, ui);
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) U[i * NV + lane + 64 * v] = ui[v];
+    }
+    double e2[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        double yn = y[v], ev = 0.0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            const double ui = U[i * NV + lane + 64 * v];
+            yn += TM[i] * ui;
+            ev += TE[i] * ui;
+        }
+        ynew[v] = yn;
+        e2[v] = 0.0;
+        if (lane + 64 * v < n) {
+            const double sc = o.atol + o.rtol * fmax(fabs(y[v]), fabs(yn));
+            const double r = ev / sc;
+            e2[v] = r * r;
+        }
+    }
+    *err = sqrt(vsum<VPL>(e2) / n);
+}
+
+template <int VPL>
+__device__ int advance_v(const DevMech &m, const DevSparse &sp, const Opts &o, double *lds, double (&y)[VPL],
+                         double p, double dt, const double *dlnA, int lane, Ctl &s)
+{
+#pragma unroll 1
+    while (true) {
+        double hc;
+        bool last;
+        const int st = ctl_begin(s, o, dt, hc, last);
+        if (st != SC_CELL_OK) return st;
+        double err, ynew[VPL];
+        ros_attempt_v<VPL>(m, sp, o, lds, y, p, dlnA, lane, hc, &err, ynew);
+        const int r = ctl_end(s, o, err, hc, last, dt);
+        if (r < 0) return -r;
+        if (r == 1) {
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) y[v] = ynew[v];
+            if (last) return SC_CELL_OK;
+        }
+    }
+}
+
+template <int VPL>
+__device__ __forceinline__ bool bad_input_v(const DevMech &m, const double (&y)[VPL], double p, double dt, int lane)
+{
+    bool bad = false;
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) bad = bad || (lane + 64 * v <= m.N && !isfinite(y[v]));
+    const double T = comp_T<VPL>(m, y);
+    return __any(bad) || !(T > 0.0) || !isfinite(T) || !(p > 0.0) || !isfinite(p) || !(dt >= 0.0) ||
+           !isfinite(dt);
+}
+
+template <int VPL>
+__device__ void integrate_cell_v(const DevMech &m, const DevSparse &sp, const Opts &o, double *lds, int64_t c,
+                                 int lane, const double *T0, const double *P, const double *Y0, int64_t ld,
+                                 const double *DT, const double *dlnA, double *h_io, double *T1, double *Y1,
+                                 int32_t *status, int32_t *nacc_out, int32_t *nrej_out)
+{
+    double y[VPL];
+    load_state_v<VPL>(m, T0, Y0, ld, c, lane, y);
+    const double p = P[c], dt = DT[c];
+    int st = SC_CELL_OK;
+    Ctl s = ctl_init(initial_step(h_io, c, dt), dt);
+    if (bad_input_v<VPL>(m, y, p, dt, lane)) {
+        st = SC_CELL_BAD_INPUT;
+    } else if (dt > 0.0) {
+        st = advance_v<VPL>(m, sp, o, lds, y, p, dt, dlnA, lane, s);
+    }
+    store_state_v<VPL>(m, T1, Y1, ld, c, lane, y);
+    if (lane == 0) {
+        status[c] = st;
+        if (nacc_out) nacc_out[c] = s.nacc;
+        if (nrej_out) nrej_out[c] = s.nrej;
+        if (h_io && st == SC_CELL_OK && dt > 0.0) h_io[c] = s.hnext;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+template <int VPL, bool CV>
+__global__ void __launch_bounds__(WAVE) k_integrate_sp(DevMech mk, DevSparse sp, Opts o, int64_t n,
+                                                       const double *T0, const double *P, const double *Y0,
+                                                       int64_t ld, const double *DT, const double *dlnA,
+                                                       double *h_io, double *T1, double *Y1, int32_t *status,
+                                                       int32_t *nacc, int32_t *nrej)
+{
+    extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
+    const int64_t c = blockIdx.x;
+    if (c >= n) return;
+    integrate_cell_v<VPL>(m, sp, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
+}
+
+template <int VPL, bool CV>
+__global__ void __launch_bounds__(WAVE) k_integrate_sp_persistent(DevMech mk, DevSparse sp, Opts o, int64_t n,
+                                                                  const double *T0, const double *P,
+                                                                  const double *Y0, int64_t ld, const double *DT,
+                                                                  const double *dlnA, double *h_io, double *T1,
+                                                                  double *Y1, int32_t *status, int32_t *nacc,
+                                                                  int32_t *nrej, unsigned long long *queue,
+                                                                  const int32_t *perm, int tile)
+{
+    extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
+    const int lane = threadIdx.x;
+#pragma unroll 1
+    while (true) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(queue, (unsigned long long)tile);
+        base = __shfl(base, 0, WAVE);
+        if (base >= (unsigned long long)n) break;
+        const int64_t end = min((int64_t)base + tile, n);
+#pragma unroll 1
+        for (int64_t i = (int64_t)base; i < end; ++i) {
+            const int64_t c = perm ? (int64_t)perm[i] : i;
+            integrate_cell_v<VPL>(m, sp, o, lds, c, lane, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc,
+                                  nrej);
+        }
+    }
+}
+
+template <int VPL, bool CV>
+__global__ void __launch_bounds__(WAVE) k_integrate_sp_static(DevMech mk, DevSparse sp, Opts o, int64_t n,
+                                                              const double *T0, const double *P, const double *Y0,
+                                                              int64_t ld, const double *DT, const double *dlnA,
+                                                              double *h_io, double *T1, double *Y1,
+                                                              int32_t *status, int32_t *nacc, int32_t *nrej,
+                                                              int64_t group)
+{
+    extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
+    const int64_t c0 = (int64_t)blockIdx.x * group;
+    const int64_t c1 = min(c0 + group, n);
+#pragma unroll 1
+    for (int64_t c = c0; c < c1; ++c)
+        integrate_cell_v<VPL>(m, sp, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc,
+                              nrej);
+}
+
+template <int VPL, bool CV>
+__global__ void __launch_bounds__(WAVE) k_rhs_sp(DevMech mk, DevSparse sp, int64_t n, const double *T,
+                                                 const double *P, const double *Y, int64_t ld, const double *dlnA,
+                                                 double *fT, double *fY)
+{
+    extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
+    const int lane = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    if (c >= n) return;
+    double y[VPL], f[VPL];
+    load_state_v<VPL>(m, T, Y, ld, c, lane, y);
+    rhs_v<VPL>(m, sp, lds, y, P[c], dlnA, lane, f);
+    store_state_v<VPL>(m, fT, fY, ld, c, lane, f);
+}
+
+// The Jacobian J (dense output, [c][i][j] over (Y, T)) recovered from the
+// bordered matrix formed with 1/hg = 0 (the -J of the scaled system with the
+// sigma border): eliminating sigma, M'_ij = A_ij + A_i,sigma A_sigma,j, and
+// undoing the scaling, J_ij = -(W_i / W_j) M'_ij (species i, j), J_iT =
+// -W_i A_iT, J_Tj = -A_Tj / W_j, J_TT = -A_TT.
+template <int VPL, bool CV>
+__global__ void __launch_bounds__(WAVE) k_jac_sp(DevMech mk, DevSparse sp, int64_t n, const double *T,
+                                                 const double *P, const double *Y, int64_t ld, const double *dlnA,
+                                                 double *J)
+{
+    extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
+    const int lane = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    if (c >= n) return;
+    double y[VPL], f[VPL];
+    load_state_v<VPL>(m, T, Y, ld, c, lane, y);
+    jac_v<VPL>(m, sp, lds, y, P[c], dlnA, lane, 0.0, f);
+    const double *E = lds + sp.E;
+    const int N = m.N, nn = N + 1, ns = sp.n;
+    const int pS = ns - 1;
+    auto A = [&](int pi, int pj) {
+        const uint16_t e = sp.emap[pi * ns + pj];
+        return e == sc::NOENT ? 0.0 : E[e];
+    };
+#pragma unroll 1
+    for (int q = lane; q < nn * nn; q += WAVE) {
+        const int i = q / nn, j = q % nn;
+        const int pi = sp.comp[CMP * i], pj = sp.comp[CMP * j];  // comp[CMP * N] is pos_T
+        double val;
+        if (i < N && j < N) val = -(m.W()[i] * m.invW()[j]) * (A(pi, pj) + A(pi, pS) * A(pS, pj));
+        else if (i < N) val = -m.W()[i] * A(pi, pj);
+        else if (j < N) val = -A(pi, pj) * m.invW()[j];
+        else val = -A(pi, pj);
+        J[(c * nn + i) * nn + j] = val;
+    }
+}
+
+template <int VPL, bool CV>
+__global__ void __launch_bounds__(WAVE) k_linsolve_sp(DevMech mk, DevSparse sp, int64_t n, const double *T,
+                                                      const double *P, const double *Y, int64_t ld,
+                                                      const double *dlnA, const double *hg, const double *b,
+                                                      double *x)
+{
+    extern __shared__ double lds[];
+    const DevMech m = fix_reactor<CV>(mk);
+    const int lane = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    if (c >= n) return;
+    double y[VPL], f[VPL], bb[VPL], xx[VPL];
+    load_state_v<VPL>(m, T, Y, ld, c, lane, y);
+    jac_v<VPL>(m, sp, lds, y, P[c], dlnA, lane, 1.0 / hg[c], f);
+    lu_v(sp, lds, lane);
+    const int nn = m.N + 1;
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int i = lane + 64 * v;
+        bb[v] = i < nn ? b[c * nn + i] : 0.0;
+    }
+    solve_v<VPL>(m, sp, lds, bb, lane, xx);
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int i = lane + 64 * v;
+        if (i < nn) x[c * nn + i] = xx[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers (host)
+// ---------------------------------------------------------------------------
+#define SP_KERNEL(k) k<VPLV, CVV>
+#define SP_DISPATCH(vpl, cv, ...)                                                        \
+    if ((vpl) == 1) {                                                                    \
+        constexpr int VPLV = 1;                                                          \
+        if (cv) { constexpr bool CVV = true; __VA_ARGS__; }                             \
+        else { constexpr bool CVV = false; __VA_ARGS__; }                               \
+    } else if ((vpl) == 2) {                                                             \
+        constexpr int VPLV = 2;                                                          \
+        if (cv) { constexpr bool CVV = true; __VA_ARGS__; }                             \
+        else { constexpr bool CVV = false; __VA_ARGS__; }                               \
+    } else {                                                                             \
+        return hipErrorInvalidValue;                                                     \
+    }
+
+static size_t sp_lds(const DevSparse &sp) { return sizeof(double) * (size_t)sp.size; }
+
+hipError_t launch_rhs_sp(int vpl, const DevMech &m, const DevSparse &sp, int64_t n, const double *T,
+                         const double *p, const double *Y, int64_t ld, const double *dlnA, double *fT, double *fY,
+                         hipStream_t s)
+{
+    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_rhs_sp), dim3((unsigned)n), dim3(WAVE), sp_lds(sp), s, m,
+                                               sp, n, T, p, Y, ld, dlnA, fT, fY));
+    return hipGetLastError();
+}
+
+hipError_t launch_jac_sp(int vpl, const DevMech &m, const DevSparse &sp, int64_t n, const double *T,
+                         const double *p, const double *Y, int64_t ld, const double *dlnA, double *J, hipStream_t s)
+{
+    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_jac_sp), dim3((unsigned)n), dim3(WAVE), sp_lds(sp), s, m,
+                                               sp, n, T, p, Y, ld, dlnA, J));
+    return hipGetLastError();
+}
+
+hipError_t launch_linsolve_sp(int vpl, const DevMech &m, const DevSparse &sp, int64_t n, const double *T,
+                              const double *p, const double *Y, int64_t ld, const double *dlnA, const double *hg,
+                              const double *b, double *x, hipStream_t s)
+{
+    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_linsolve_sp), dim3((unsigned)n), dim3(WAVE), sp_lds(sp),
+                                               s, m, sp, n, T, p, Y, ld, dlnA, hg, b, x));
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate_sp(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o, int64_t n,
+                               const double *T0, const double *p, const double *Y0, int64_t ld, const double *dt,
+                               const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na,
+                               int32_t *nr, hipStream_t s)
+{
+    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp), dim3((unsigned)n), dim3(WAVE), sp_lds(sp),
+                                               s, m, sp, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr));
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate_sp_persistent(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o,
+                                          int64_t n, const double *T0, const double *p, const double *Y0,
+                                          int64_t ld, const double *dt, const double *dlnA, double *h_io,
+                                          double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr,
+                                          unsigned long long *queue, const int32_t *perm, int tile, int grid,
+                                          hipStream_t s)
+{
+    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp_persistent), dim3((unsigned)grid),
+                                               dim3(WAVE), sp_lds(sp), s, m, sp, o, n, T0, p, Y0, ld, dt, dlnA,
+                                               h_io, T1, Y1, st, na, nr, queue, perm, tile));
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate_sp_static(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o, int64_t n,
+                                      const double *T0, const double *p, const double *Y0, int64_t ld,
+                                      const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
+                                      int32_t *st, int32_t *na, int32_t *nr, int grid, hipStream_t s)
+{
+    const int64_t group = (n + grid - 1) / grid;
+    const unsigned g = (unsigned)((n + group - 1) / group);
+    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp_static), dim3(g), dim3(WAVE), sp_lds(sp), s,
+                                               m, sp, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr,
+                                               group));
+    return hipGetLastError();
+}
+
+int persistent_capacity_sp(int vpl, const DevSparse &sp, int device)
+{
+    int per_cu = 0, cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (vpl == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_sp_persistent<1, false>, WAVE,
+                                                         sp_lds(sp));
+    else if (vpl == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_sp_persistent<2, false>, WAVE,
+                                                         sp_lds(sp));
+    return e == hipSuccess ? per_cu * cus : 0;
+}
+
+}  // namespace scdev

@@ -85,16 +85,40 @@ def equilibrium_tp(mech, T, p, b, iters=200, tol=1e-13):
     excl = excl.any(axis=1)
     mu0 = np.where(excl, -np.inf, mu0)
     lnb = np.log(np.where(present, b / b.sum(1, keepdims=True), 1.0))
+    logA = np.where(A > 0, np.log(np.where(A > 0, A, 1.0)), -np.inf)  # [E, N]
+    lam, done = _newton(A, logA, mu0, present, lnb, iters, tol, damped=False)
+    if not done.all():
+        # Newton can cycle on strongly lopsided element mixtures: those cells
+        # start again with a backtracking line search on the residual
+        bad = np.nonzero(~done)[0]
+        lam_b, done_b = _newton(A, logA, mu0[bad], present[bad], lnb[bad], iters, tol, damped=True)
+        lam[bad] = lam_b
+        if not done_b.all():
+            raise RuntimeError(f"equilibrium did not converge for {np.sum(~done_b)} cells")
+    lnx = mu0 + lam @ A
+    lnx -= _logsumexp(lnx)[:, None]
+    return np.exp(lnx)
+
+
+def _newton(A, logA, mu0, present, lnb, iters, tol, damped):
+    """Newton on the element-potential equations (see equilibrium_tp);
+    returns (lambda, converged).  damped: halve each step until the largest
+    residual decreases (at most 40 times)."""
+    E = A.shape[0]
+    nc = mu0.shape[0]
     lam = np.zeros((nc, E))
     lnt = np.zeros(nc)
-    logA = np.where(A > 0, np.log(np.where(A > 0, A, 1.0)), -np.inf)  # [E, N]
-    done = np.zeros(nc, bool)
-    for it in range(iters):
-        lnx = mu0 + lam @ A  # [nc, N]
+
+    def residual(lam_, lnt_):
+        lnx = mu0 + lam_ @ A  # [nc, N]
         r0 = _logsumexp(lnx)
         lnAx = _logsumexp(lnx[:, None, :] + logA[None, :, :])  # [nc, E]
-        re = np.where(present, lnAx - lnb - lnt[:, None], 0.0)
-        res = np.concatenate([r0[:, None], re], axis=1)
+        re = np.where(present, lnAx - lnb - lnt_[:, None], 0.0)
+        return np.concatenate([r0[:, None], re], axis=1), lnx, r0, lnAx
+
+    done = np.zeros(nc, bool)
+    for it in range(iters):
+        res, lnx, r0, lnAx = residual(lam, lnt)
         err = np.abs(res).max(1)
         done = err < tol
         if done.all():
@@ -118,14 +142,18 @@ def equilibrium_tp(mech, T, p, b, iters=200, tol=1e-13):
         scale = np.minimum(1.0, 4.0 / np.maximum(step, 1e-300))
         d *= scale[:, None]
         d[done] = 0.0
+        if damped:
+            alpha = np.ones(nc)
+            for _ in range(40):
+                rt = np.abs(residual(lam + alpha[:, None] * d[:, :E], lnt + alpha * d[:, E])[0]).max(1)
+                worse = (rt >= err) & ~done
+                if not worse.any():
+                    break
+                alpha[worse] *= 0.5
+            d *= alpha[:, None]
         lam += d[:, :E]
         lnt += d[:, E]
-    else:
-        if not done.all():
-            raise RuntimeError(f"equilibrium did not converge for {np.sum(~done)} cells")
-    lnx = mu0 + lam @ A
-    lnx -= _logsumexp(lnx)[:, None]
-    return np.exp(lnx)
+    return lam, done
 
 
 def mole_to_mass(mech, x):

@@ -178,11 +178,20 @@ def test_integrate_tight_tolerance_parity(torch, sc, key, golden):
     assert np.all(ex <= 1.0), (ex.max(), idx[np.argmax(ex)])
 
 
+# G2 band: at the production tolerance the integrator's own global error is
+# of the order of rtol, so the literal bar (excess <= 1) is reported, not
+# gated; what is gated is that every component (T, Y above and below the
+# 1e-8 floor) stays within G2_BAND times the bar on every cell.
+G2_BAND = 1000.0
+
+
 @pytest.mark.parametrize("key,golden", [("C1", "c1_ref.npz"), ("C2", "c2_ref.npz")])
 def test_integrate_production_tolerance(torch, sc, key, golden):
-    """Gate G2 (reported): at the workload tolerance rtol 1e-6 / atol 1e-12
-    the pass fraction of the literal bar; the test requires every cell to
-    finish and the error to stay within the controller's 100x rtol band."""
+    """Gate G2: at the workload tolerance rtol 1e-6 / atol 1e-12, every cell
+    finishes and every component's error is within G2_BAND times the parity
+    bar (T and Y > 1e-8 relative 1e-3, Y <= 1e-8 absolute 1e-9); the pass
+    fraction of the literal bar (excess <= 1) and the worst excess are printed
+    (the bench line reports them on the full stored sample)."""
     c = cells(key)
     g = _golden(golden)
     idx = g["idx"]
@@ -193,8 +202,15 @@ def test_integrate_production_tolerance(torch, sc, key, golden):
     assert np.all(st == 0)
     Tg, Yg = r["T"].cpu().numpy(), r["Y"].cpu().numpy().T
     ex = parity_excess(Tg, Yg, g["T"], g["Y"])
-    print(f"{key}: G2 pass fraction {np.mean(ex <= 1):.3f}, worst excess {ex.max():.3g}")
-    assert np.all(np.abs(Tg - g["T"]) <= 1e-4 * g["T"])
+    big = np.abs(g["Y"]) > 1e-8
+    exT = np.abs(Tg - g["T"]) / (1e-6 * g["T"])
+    exYb = np.where(big, np.abs(Yg - g["Y"]) / (1e-6 * np.abs(g["Y"]) + 1e-300), 0.0).max(1)
+    exYs = np.where(big, 0.0, np.abs(Yg - g["Y"]) / 1e-12).max(1)
+    print(f"{key}: G2 pass fraction {np.mean(ex <= 1):.3f} of {ex.size} cells, worst excess {ex.max():.3g} "
+          f"(T {exT.max():.3g}, Y > 1e-8 {exYb.max():.3g}, Y <= 1e-8 {exYs.max():.3g}), "
+          f"p99 {np.percentile(ex, 99):.3g}")
+    assert exT.max() <= G2_BAND and exYb.max() <= G2_BAND and exYs.max() <= G2_BAND, (
+        exT.max(), exYb.max(), exYs.max(), idx[np.argmax(ex)])
 
 
 def test_conservation(torch, sc):

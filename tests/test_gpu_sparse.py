@@ -1,0 +1,174 @@
+"""The sparse linear algebra kernels (the bordered system in minimum-degree
+order, factorised and solved by the mechanism compiler's static level
+schedule) through the C ABI: right-hand side, Jacobian and linear solve
+against the oracle's definition, complex-step Jacobian and dense solve, for
+the 9-, 53- and 110-species mechanisms (the last needs two state components
+per lane); integration at rtol 1e-10 against the converged oracle references
+(parity bar: T and Y > 1e-8 relative 1e-6, Y below absolute 1e-12); launch
+modes bit for bit."""
+import os
+
+import numpy as np
+import pytest
+
+from test_gpu_parity import cells, gross_scale, parity_excess, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KEYS = [("C1", 64), ("C2", 48), ("C3", 24)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a HIP device"
+    return t
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import paper_2311_14941_amd as m
+    m.ensure_built()
+    return m
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    from oracle import oracle as o
+    return o
+
+
+def _sample(c, n, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(c["T"].size, n, replace=False))
+
+
+@pytest.mark.parametrize("key,ncell", KEYS)
+def test_sparse_rhs_parity(torch, sc, oracle_mod, key, ncell):
+    c = cells(key)
+    mech = c["mech"]
+    idx = _sample(c, ncell, 0)
+    plan = sc.Plan(sc.Mechanism(mech.to_text()), linalg="sparse")
+    T, p, Y, _ = to_gpu(torch, c, idx)
+    rng = np.random.default_rng(1)
+    dlnA = rng.normal(size=mech.n_reactions) * 0.3
+    fT, fY = plan.rhs(T, p, Y, dlnA=dlnA)
+    fT, fY = fT.cpu().numpy(), fY.cpu().numpy().T
+    o = oracle_mod.Oracle(mech.to_text())
+    worst = 0.0
+    for n, i in enumerate(idx):
+        f = o.rhs(np.append(c["Y"][i], c["T"][i]), c["p"][i], dlnA=dlnA)
+        sY, sT = gross_scale(o, mech, c["T"][i], c["p"][i], c["Y"][i], dlnA)
+        worst = max(worst, (np.abs(fY[n] - f[:-1]) / (sY + 1e-300)).max(), abs(fT[n] - f[-1]) / (sT + 1e-300))
+    assert worst < 1e-12, worst
+
+
+@pytest.mark.parametrize("key,ncell", KEYS)
+@pytest.mark.parametrize("reactor", ["const_p", "const_v"])
+def test_sparse_jacobian_parity(torch, sc, oracle_mod, key, ncell, reactor):
+    """The Jacobian recovered from the bordered matrix (sigma eliminated,
+    scaling undone) against the oracle's complex-step J, both reactors."""
+    c = cells(key)
+    mech = c["mech"]
+    idx = _sample(c, ncell, 2)
+    T, p, Y, _ = to_gpu(torch, c, idx)
+    pa = c["p"][idx]
+    if reactor == "const_v":
+        W = mech.molar_masses()
+        pa = c["p"][idx] / (8.314462618 * c["T"][idx] * (c["Y"][idx] / W).sum(1))
+        p = torch.tensor(pa, device="cuda:0")
+    plan = sc.Plan(sc.Mechanism(mech.to_text()), linalg="sparse", reactor=reactor)
+    rng = np.random.default_rng(3)
+    dlnA = rng.normal(size=mech.n_reactions) * 0.3
+    J = plan.jacobian(T, p, Y, dlnA=dlnA).cpu().numpy()
+    o = oracle_mod.Oracle(mech.to_text())
+    worst = 0.0
+    for n, i in enumerate(idx):
+        Jc = o.jac_cs(np.append(c["Y"][i], c["T"][i]), pa[n], dlnA=dlnA, constv=reactor == "const_v")
+        row = np.abs(Jc).max(1, keepdims=True) + 1e-300
+        worst = max(worst, (np.abs(J[n] - Jc) / (1e-8 * np.abs(Jc) + 1e-12 * row)).max())
+    assert worst <= 1.0, worst
+
+
+@pytest.mark.parametrize("key,ncell", KEYS)
+def test_sparse_linsolve_parity(torch, sc, oracle_mod, key, ncell):
+    """(I/hg - J) x = b through the bordered sparse LU (no pivoting, static
+    minimum-degree order) against a dense solve of the complex-step matrix:
+    residual and solution."""
+    c = cells(key)
+    mech = c["mech"]
+    idx = _sample(c, ncell, 4)
+    plan = sc.Plan(sc.Mechanism(mech.to_text()), linalg="sparse")
+    T, p, Y, _ = to_gpu(torch, c, idx)
+    n, m = idx.size, mech.n_species + 1
+    rng = np.random.default_rng(5)
+    b = rng.normal(size=(n, m))
+    o = oracle_mod.Oracle(mech.to_text())
+    for hg in (1e-9, 1e-6, 1e-3):
+        x = plan.linsolve(T, p, Y, np.full(n, hg), b).cpu().numpy()
+        for k, i in enumerate(idx):
+            A = np.eye(m) / hg - o.jac_cs(np.append(c["Y"][i], c["T"][i]), c["p"][i])
+            ref = np.linalg.solve(A, b[k])
+            res = np.abs(A @ x[k] - b[k]).max() / (np.abs(A).max() * np.abs(x[k]).max() + np.abs(b[k]).max())
+            assert res < 1e-12, (hg, i, res)
+            assert np.allclose(x[k], ref, rtol=1e-7, atol=1e-9 * np.abs(ref).max()), (hg, i)
+
+
+@pytest.mark.parametrize("key,golden", [("C1", "c1_ref.npz"), ("C2", "c2_ref.npz"), ("C3", "c3_ref.npz")])
+def test_sparse_integrate_tight_tolerance_parity(torch, sc, key, golden):
+    """Gate G1 for the sparse kernels: at rtol 1e-10 / atol 1e-16 every
+    stored reference cell meets the parity bar (the 110-species C3 cells
+    have per-cell dt from 1e-7 to 1e-3 s)."""
+    c = cells(key)
+    g = np.load(os.path.join(HERE, "golden", golden))
+    idx = g["idx"]
+    plan = sc.Plan(sc.Mechanism(c["mech"].to_text()), rtol=1e-10, atol=1e-16, max_steps=200000, linalg="sparse")
+    T, p, Y, dt = to_gpu(torch, c, idx)
+    r = plan.integrate(T, p, Y, dt)
+    st = r["status"].cpu().numpy()
+    assert np.all(st == 0), np.bincount(st)
+    ex = parity_excess(r["T"].cpu().numpy(), r["Y"].cpu().numpy().T, g["T"], g["Y"])
+    print(f"{key} sparse: worst parity excess {ex.max():.3g} over {idx.size} cells (<= 1 passes)")
+    assert np.all(ex <= 1.0), (ex.max(), idx[np.argmax(ex)])
+
+
+@pytest.mark.parametrize("key", ["C2", "C3"])
+def test_sparse_launch_modes_bitwise(torch, sc, key):
+    """Plain, static and queue launches of the sparse kernels give the same
+    bits; so does the allocation-free entry point."""
+    c = cells(key)
+    idx = _sample(c, 2048, 6)
+    T, p, Y, dt = to_gpu(torch, c, idx)
+    mech = sc.Mechanism(c["mech"].to_text())
+    a = sc.Plan(mech, linalg="sparse").integrate(T, p, Y, dt)
+    assert np.all(a["status"].cpu().numpy() == 0)
+    for cfg in (dict(mode="static"), dict(mode="persistent", order="cost")):
+        q = sc.Plan(mech, linalg="sparse", **cfg)
+        b = q.integrate(T, p, Y, dt)
+        b = q.integrate(T, p, Y, dt, out=b)
+        for k in ("T", "Y", "status", "n_acc", "n_rej"):
+            assert torch.equal(a[k], b[k]), (cfg, k)
+    q = sc.Plan(mech, linalg="sparse", mode="persistent", order="dt")
+    b = q.integrate_noalloc(T, p, Y, dt)
+    for k in ("T", "Y", "status", "n_acc", "n_rej"):
+        assert torch.equal(a[k], b[k]), ("noalloc", k)
+
+
+def test_sparse_matches_dense_and_conserves(torch, sc):
+    """On the 53-species workload the sparse and dense kernels integrate the
+    same ODE: at rtol 1e-10 they agree to the parity bar, and both keep the
+    sum of mass fractions and the element totals to roundoff."""
+    c = cells("C2")
+    idx = _sample(c, 1024, 7)
+    T, p, Y, dt = to_gpu(torch, c, idx)
+    mech = sc.Mechanism(c["mech"].to_text())
+    s = sc.Plan(mech, rtol=1e-10, atol=1e-16, linalg="sparse").integrate(T, p, Y, dt)
+    d = sc.Plan(mech, rtol=1e-10, atol=1e-16, linalg="dense").integrate(T, p, Y, dt)
+    ex = parity_excess(s["T"].cpu().numpy(), s["Y"].cpu().numpy().T, d["T"].cpu().numpy(),
+                       d["Y"].cpu().numpy().T)
+    assert ex.max() <= 1.0, ex.max()
+    Y0, Y1 = c["Y"][idx], s["Y"].cpu().numpy().T
+    assert np.abs(Y1.sum(1) - Y0.sum(1)).max() < 1e-13
+    A = c["mech"].element_matrix() / c["mech"].molar_masses()[None, :]
+    assert np.abs(Y1 @ A.T - Y0 @ A.T).max() < 1e-12 * np.abs(Y0 @ A.T).max()

@@ -95,9 +95,21 @@ def test_merged_coefficients_and_duplicate_efficiencies_are_rejected():
 
 
 def test_oversized_mechanism_is_unsupported():
+    """Up to 127 species load (the sparse kernels hold two state components
+    per lane); 130 do not."""
+    import copy
+    from synth.mechgen import Mechanism
+    base = standard_mechanism("chon_110")
+    sc.Mechanism(base.to_text())
+    extra = []
+    for i in range(20):
+        s = copy.deepcopy(base.species[i])
+        s.name = f"{s.name}_X{i}"
+        extra.append(s)
+    big = Mechanism(elements=base.elements, species=base.species + extra, reactions=base.reactions, name="big")
     with pytest.raises(sc.StiffchemError) as e:
-        sc.Mechanism(standard_mechanism("chon_110").to_text())
-    assert e.value.code == sc.SC_EUNSUPPORTED
+        sc.Mechanism(big.to_text())
+    assert e.value.code == sc.SC_EUNSUPPORTED and "127" in str(e.value)
 
 
 def test_null_arguments_rejected_before_any_device_call():
