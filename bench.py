@@ -90,10 +90,12 @@ def main():
     ap.add_argument("--spinup", type=int, default=400,
                     help="lts workload: untimed split steps before the warm-up and the timed steps")
     ap.add_argument("--no-gradient", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c2v", "c3", "c5", "lts", "copy"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c2v", "c3", "c3s", "c5", "c5s", "lts", "copy"],
                     help="c2: the headline (default); c2v: the same cells as constant-volume reactors; "
-                         "c3: the uneven batch, queue vs static mapping; "
-                         "c5: 20 chained substeps, forward and gradient; lts: split steps (chemistry + "
+                         "c3: the uneven batch on the 110-species mechanism, queue vs static mapping "
+                         "(c3s: on the 53-species one); "
+                         "c5: 20 chained substeps of the 110-species mechanism, forward and gradient "
+                         "(c5s: 53 species); lts: split steps (chemistry + "
                          "transport) of the 170 x 170 flame field with local time steps; copy: a plain "
                          "device copy of known size (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -107,9 +109,9 @@ def main():
     from synth.cells import make_cells
 
     sc.ensure_built()
-    if args.workload == "c3":
+    if args.workload in ("c3", "c3s"):
         return bench_uneven(args)
-    if args.workload == "c5":
+    if args.workload in ("c5", "c5s"):
         return bench_chained(args)
     if args.workload == "copy":
         return bench_copy(args)
@@ -471,8 +473,9 @@ def bench_chained(args):
     import torch
     import paper_2311_14941_amd as sc
     from synth.cells import make_cells
-    log("bench: generating the chained-substep batch")
-    c = make_cells("C5s")
+    key = "C5" if args.workload == "c5" else "C5s"
+    log(f"bench: generating the chained-substep batch {key}")
+    c = make_cells(key)
     nsub = c["substeps"]
     dev = "cuda:0"
     T = torch.tensor(c["T"], device=dev)
@@ -480,7 +483,8 @@ def bench_chained(args):
     Y = torch.tensor(np.ascontiguousarray(c["Y"].T), device=dev)
     dt = torch.tensor(c["dt"], device=dev)
     mech = sc.Mechanism(c["mech"].to_text())
-    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12)
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, linalg=args.linalg)
+    plan.adjoint_budget = 64 << 30  # the workload's device-memory cap for the adjoint's checkpoints
     k_no = next(k for k, s_ in enumerate(c["mech"].species) if s_.comp == {"N": 1, "O": 1})
     log("bench: capture + forward")
     chain = sc.Chain(plan, T, p, Y, dt, nsub)
@@ -512,8 +516,9 @@ def bench_chained(args):
     line = {"metric": "chained substeps: forward and gradient wall time", "unit": "ms",
             "value": (t2 - t1) * 1e3 / fwd_ms, "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
             "data": "synthetic",
-            "config": {"workload": "65,536 cells, 53-species mechanism, C2 classes, 20 chained substeps of "
-                                   "5e-5 s (state and step size carried), rtol 1e-6", "substeps": nsub},
+            "config": {"workload": f"{key}: 65,536 cells, {mech.N}-species mechanism, C2 classes, 20 chained "
+                                   "substeps of 5e-5 s (state and step size carried), rtol 1e-6, adjoint "
+                                   "workspace capped at 64 GB", "substeps": nsub, "linalg": args.linalg},
             "forward_graph_ms": fwd_ms, "autograd_forward_ms": (t1 - t0) * 1e3,
             "backward_ms": (t2 - t1) * 1e3, "gradient_forward_ratio": (t2 - t1) * 1e3 / fwd_ms,
             "graph_and_autograd_forward_identical": same,
@@ -569,16 +574,21 @@ def gradient_ratio(sc, torch, mech_text, launch, reps=3, hmax_frac=0.0):
 
 
 def bench_uneven(args):
-    """Uneven batch: 262,144 cells of the C2 classes with per-cell dt
-    log-uniform in [1e-7, 1e-3] s (step counts spread > 100x), 53-species
-    mechanism.  Static cell-to-workgroup mapping (baseline) against the
-    persistent queue in the configuration the autotuner picks."""
+    """Uneven batch C3: 262,144 cells of the C2 classes with per-cell dt
+    log-uniform in [1e-7, 1e-3] s (step counts spread > 100x) on the seeded
+    110-species / 700-reaction mechanism (sparse linear algebra: two state
+    components per lane), or with --workload c3s the same batch on the
+    53-species mechanism.  Static cell-to-workgroup mapping and the plain
+    one-workgroup-per-cell launch (baselines) against the persistent queue
+    in the configuration the autotuner picks; cost orders sort by predicted
+    counts (a perturbed copy of the batch), never the call's own."""
     import torch
     import paper_2311_14941_amd as sc
     from paper_2311_14941_amd import autotune
     from synth.cells import make_cells
-    log("bench: generating the uneven batch")
-    cells = make_cells("C3s")
+    key = "C3s" if args.workload == "c3s" else "C3"
+    log(f"bench: generating the uneven batch {key}")
+    cells = make_cells(key)
     n = cells["T"].size
     dev = "cuda:0"
     T = torch.tensor(cells["T"], device=dev)
@@ -586,18 +596,24 @@ def bench_uneven(args):
     Y = torch.tensor(np.ascontiguousarray(cells["Y"].T), device=dev)
     dt = torch.tensor(cells["dt"], device=dev)
     mech = sc.Mechanism(cells["mech"].to_text())
+    log("bench: predicted cost from a perturbed copy of the batch")
+    pred = predicted_cost(sc, torch, mech, T, p, Y, dt, "const_p", "ros4")
     log("bench: autotuning on a 16,384-cell sample")
     s = np.random.default_rng(0).choice(n, 16384, replace=False)
     ts = torch.tensor(s, device=dev)
     best, times = autotune.tune(mech, T[ts].contiguous(), p[ts].contiguous(), Y[:, ts].contiguous(),
-                                dt[ts].contiguous(), use_cache=False, reps=1, verbose=True)
+                                dt[ts].contiguous(), use_cache=False, reps=1, verbose=True, linalg=args.linalg,
+                                cost=(pred[0][ts].contiguous(), pred[1][ts].contiguous()))
 
-    def timed(plan, prev=None):
-        out = plan.integrate(T, p, Y, dt) if prev is None else prev
+    def timed(plan, cost):
+        out = plan.integrate(T, p, Y, dt)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ms = []
         for _ in range(args.steps):
+            if cost is not None:
+                out["n_acc"].copy_(cost[0])
+                out["n_rej"].copy_(cost[1])
             a.record()
             out = plan.integrate(T, p, Y, dt, out=out)
             b.record()
@@ -605,23 +621,41 @@ def bench_uneven(args):
             ms.append(a.elapsed_time(b))
         return float(np.median(ms)), out
 
-    res = {}
+    res, ref = {}, None
     for name, cfg in (("static", dict(mode="static")), ("plain", dict(mode="plain")),
+                      ("persistent_index_order", dict(mode="persistent", order="none")),
                       ("persistent_tuned", best)):
         log(f"bench: {name}")
-        ms, out = timed(sc.Plan(mech, **cfg))
+        cost = pred if cfg.get("order") == "cost" else None
+        ms, out = timed(sc.Plan(mech, linalg=args.linalg, **cfg), cost)
         res[name] = ms
+        if ref is None:
+            ref = out
+        res[name + "_identical"] = bool(torch.equal(ref["T"], out["T"]) and torch.equal(ref["Y"], out["Y"]))
+    # the exact-count order (the batch's own counts: an upper bound)
+    ms, _ = timed(sc.Plan(mech, linalg=args.linalg, mode="persistent", order="cost"),
+                  (ref["n_acc"].clone(), ref["n_rej"].clone()))
+    res["persistent_cost_exact_upper_bound"] = ms
     steps = (out["n_acc"] + out["n_rej"]).cpu().numpy()
+    st = out["status"].cpu().numpy()
+    N = mech.N
     line = {"metric": "uneven batch: cells/s, persistent queue vs static mapping", "unit": "cells/s",
             "value": n / (res["persistent_tuned"] / 1e3), "n_gpus": 1, "steps": args.steps,
             "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "262,144 cells, 53-species mechanism, C2 classes, dt log-uniform 1e-7..1e-3 s, "
-                                   "rtol 1e-6", "tuned": best},
+            "config": {"workload": f"{key}: 262,144 cells, {N}-species/{mech.R}-reaction mechanism, C2 classes, "
+                                   "dt log-uniform 1e-7..1e-3 s, rtol 1e-6, atol 1e-12", "tuned": best,
+                       "linalg": args.linalg, "kernel": kernel_name(best, args.linalg, N),
+                       "failed_cells": int(np.sum(st != 0))},
             "ms": res, "speedup_vs_static": res["static"] / res["persistent_tuned"],
             "speedup_vs_plain": res["plain"] / res["persistent_tuned"],
             "steps_per_cell": {"mean": float(steps.mean()), "p50": float(np.median(steps)),
-                               "max": int(steps.max()), "spread_max_over_p10": float(steps.max() / max(1, np.percentile(steps, 10)))},
+                               "p10": float(np.percentile(steps, 10)), "max": int(steps.max()),
+                               "spread_max_over_p10": float(steps.max() / max(1, np.percentile(steps, 10)))},
             "tuning_sample_ms": times}
+    flops = float(steps.sum()) * mech.info["flops_step_sparse"]
+    achieved = flops / (res["persistent_tuned"] / 1e3) / 1e12
+    line["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "flops_per_launch": flops}
     print(json.dumps(line), flush=True)
 
 

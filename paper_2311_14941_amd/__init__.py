@@ -402,7 +402,8 @@ def _chem_integrate_fn():
             plan = ctx.plan
             gT1 = torch.zeros_like(T0) if gT1 is None else gT1.contiguous()
             gY1 = torch.zeros_like(Y0) if gY1 is None else gY1.contiguous()
-            r = plan.adjoint(T0, p, Y0, dt, gT1, gY1, dlnA=dlnA if ctx.has_dlnA else None, h=hin, cost=cost)
+            r = plan.adjoint(T0, p, Y0, dt, gT1, gY1, dlnA=dlnA if ctx.has_dlnA else None, h=hin, cost=cost,
+                             budget=getattr(plan, "adjoint_budget", 0))
             g_d = r["g_dlnA"] if ctx.has_dlnA and ctx.needs_input_grad[2] else None
             return r["gT0"], r["gY0"], g_d, None, None, None, None
 

@@ -399,14 +399,17 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
         comp[(size_t)scdev::CMP * N] = S.pos[N];
         comp[(size_t)scdev::CMP * N + 1] = S.e_TT;
         comp[(size_t)scdev::CMP * N + 2] = S.e_SS;
-        std::vector<uint16_t> emap(S.emap.size());
+        std::vector<uint16_t> emap(S.emap.size()), colmap(S.emap.size());
         for (size_t i = 0; i < emap.size(); ++i) emap[i] = S.emap[i] < 0 ? sc::NOENT : (uint16_t)S.emap[i];
+        for (int r = 0; r < S.n; ++r)
+            for (int k = 0; k < S.n; ++k) colmap[(size_t)k * S.n + r] = emap[(size_t)r * S.n + k];
         scdev::DevSparse &q = p->ds;
+        std::vector<uint64_t> lu_b(S.lu_b.begin(), S.lu_b.end());
         ok = upload(p, S.lu_b_lvl, &q.lu_b_lvl) && upload(p, S.lu_c_lvl, &q.lu_c_lvl) &&
-             upload(p, S.fw_lvl, &q.fw_lvl) && upload(p, S.bw_lvl, &q.bw_lvl) && upload(p, S.lu_b, &q.lu_b) &&
+             upload(p, S.fw_lvl, &q.fw_lvl) && upload(p, S.bw_lvl, &q.bw_lvl) && upload(p, lu_b, &q.lu_b) &&
              upload(p, S.lu_u, &q.lu_u) && upload(p, S.diag, &q.diag) && upload(p, S.lu_c, &q.lu_c) &&
              upload(p, S.fw, &q.fw) && upload(p, S.bw, &q.bw) && upload(p, rxi, &q.rxi) &&
-             upload(p, comp, &q.comp) && upload(p, emap, &q.emap);
+             upload(p, comp, &q.comp) && upload(p, emap, &q.emap) && upload(p, colmap, &q.colmap);
     }
     if (ok) {
         void *q = nullptr;

@@ -54,11 +54,13 @@ struct DevSparse {
     int E, C, G, H, WD, UA, U, X, DINV, size;
     int NV;
     const int *lu_b_lvl, *lu_c_lvl, *fw_lvl, *bw_lvl;
-    const uint32_t *lu_b, *lu_u, *diag;
+    const uint64_t *lu_b;  // widened to the c items' width: e_ik | e_kk << 16
+    const uint32_t *lu_u, *diag;
     const uint64_t *lu_c, *fw, *bw;
     const uint16_t *rxi;   // [R][RXI_SIZE], reaction execution order
     const int32_t *comp;   // per species k: pos, e_kk, e_kT, e_kS, e_Tk, e_Sk; then pos_T, e_TT, e_SS
-    const uint16_t *emap;  // n * n: (row, column) position -> entry or NOENT
+    const uint16_t *emap;    // n * n: (row, column) position -> entry or NOENT, row-major
+    const uint16_t *colmap;  // the same map column-major: colmap[k * n + i] = entry of (i, k)
 };
 constexpr int CMP = 6;  // comp entries per species
 

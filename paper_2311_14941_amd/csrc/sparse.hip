@@ -292,35 +292,78 @@ __device__ __forceinline__ void run_items(const uint64_t *items, int q0, int q1,
     }
 }
 
+// The first four 64-item groups of a phase, loaded ahead (the loads of the
+// next phase are issued before the current one is processed, so their
+// latency overlaps its LDS work).
+struct Pre {
+    uint64_t it[4];
+};
+__device__ __forceinline__ Pre preload(const uint64_t *items, int q0, int q1, int lane)
+{
+    Pre p;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * WAVE + lane;
+        p.it[u] = q < q1 ? items[q] : ~0ull;
+    }
+    return p;
+}
+
+// l_ik = a_ik / a_kk for the items of one phase (b items: e_ik | e_kk << 16)
+__device__ __forceinline__ void lu_scale_items(double *E, const uint64_t (&it)[4])
+{
+    double a[4], d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const bool ok = it[u] != ~0ull;
+        a[u] = ok ? E[lo16(it[u])] : 0.0;
+        d[u] = ok ? E[mid16(it[u])] : 1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (it[u] != ~0ull) E[lo16(it[u])] = a[u] / d[u];
+}
+
+// a_ij -= l_ik u_kj for the items of one phase (c items: e_ij | e_ik << 16 | e_kj << 32)
+__device__ __forceinline__ void lu_update_items(double *E, const uint64_t (&it)[4])
+{
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const bool ok = it[u] != ~0ull;
+        a[u] = ok ? E[mid16(it[u])] : 0.0;
+        b[u] = ok ? E[hi16(it[u])] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (it[u] != ~0ull) atomicAdd(&E[lo16(it[u])], -a[u] * b[u]);
+}
+
 // Numeric LU of the formed matrix in E by the static level schedule, then
 // dinv = 1/u_kk and the rows of U scaled to a unit diagonal.
 __device__ void lu_v(const DevSparse &sp, double *lds, int lane)
 {
     double *E = lds + sp.E;
     double *DINV = lds + sp.DINV;
+    Pre pre = preload(sp.lu_b, sp.lu_b_lvl[0], sp.lu_b_lvl[1], lane);
 #pragma unroll 1
     for (int l = 0; l < sp.nl_lu; ++l) {
         const int b0 = sp.lu_b_lvl[l], b1 = sp.lu_b_lvl[l + 1];
-#pragma unroll 1
-        for (int q = b0 + lane; q < b1; q += WAVE) {
-            const uint32_t it = sp.lu_b[q];
-            const int eik = (int)(it & 0xffff), ekk = (int)(it >> 16);
-            E[eik] = E[eik] / E[ekk];
-        }
-        __syncthreads();
         const int c0 = sp.lu_c_lvl[l], c1 = sp.lu_c_lvl[l + 1];
+        Pre cur = pre;
+        pre = preload(sp.lu_c, c0, c1, lane);
+        lu_scale_items(E, cur.it);
+#pragma unroll 1
+        for (int base = b0 + 4 * WAVE; base < b1; base += 4 * WAVE)
+            lu_scale_items(E, preload(sp.lu_b, base, b1, lane).it);
+        __syncthreads();
+        cur = pre;
+        if (l + 1 < sp.nl_lu) pre = preload(sp.lu_b, b1, sp.lu_b_lvl[l + 2], lane);
         if (c1 > c0) {
-            run_items(sp.lu_c, c0, c1, lane, [&](const uint64_t (&it)[4], const bool (&ok)[4]) {
-                double a[4], b[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    a[u] = ok[u] ? E[mid16(it[u])] : 0.0;
-                    b[u] = ok[u] ? E[hi16(it[u])] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (ok[u]) atomicAdd(&E[lo16(it[u])], -a[u] * b[u]);
-            });
+            lu_update_items(E, cur.it);
+#pragma unroll 1
+            for (int base = c0 + 4 * WAVE; base < c1; base += 4 * WAVE)
+                lu_update_items(E, preload(sp.lu_c, base, c1, lane).it);
             __syncthreads();
         }
     }
@@ -357,11 +400,23 @@ __device__ __forceinline__ void sweep(const double *E, double *X, const int *lvl
 }
 
 // Solve M x = b with the factors in E (b, x: VPL components per lane).
+// The vector is moved to position order and swept in registers, one column
+// of L (then of the unit-diagonal U) per iteration: the pivot value is
+// broadcast with readlane and every lane whose row holds an entry in that
+// column updates its component; entries come from the column-major entry
+// map.  No barrier inside the sweeps (one wave).
+template <int VPL>
+__device__ __forceinline__ double rd_pos(const double (&z)[VPL], int k)
+{
+    if (VPL == 1 || k < 64) return rdlane(z[0], k);
+    return rdlane(z[VPL - 1], k - 64);
+}
+
 template <int VPL>
 __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&b)[VPL], int lane,
                         double (&x)[VPL])
 {
-    const int N = m.N;
+    const int N = m.N, n = sp.n;
     const double *E = lds + sp.E;
     double *X = lds + sp.X;
     const double *DINV = lds + sp.DINV;
@@ -371,13 +426,66 @@ __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, cons
         if (c < N) X[sp.comp[CMP * c]] = b[v] * m.invW()[c];
         if (c == N) X[sp.comp[CMP * N]] = b[v];
     }
-    if (lane == 0) X[sp.n - 1] = 0.0;  // sigma row
+    if (lane == 0) X[n - 1] = 0.0;  // sigma row
     __syncthreads();
-    sweep(E, X, sp.fw_lvl, sp.fw, sp.nl_fw, lane);
-#pragma unroll 1
-    for (int k = lane; k < sp.n; k += WAVE) X[k] *= DINV[k];
+    double z[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int q = lane + 64 * v;
+        z[v] = q < n ? X[q] : 0.0;
+    }
+    // forward: x_i -= l_ik x_k, k ascending (the next column's entry
+    // indices are loaded one iteration ahead)
+    uint16_t enx[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int q = lane + 64 * v;
+        enx[v] = q < n ? sp.colmap[q] : sc::NOENT;
+    }
+    for (int k = 0; k < n - 1; ++k) {
+        uint16_t e[VPL];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+            const int q = lane + 64 * v;
+            e[v] = q > k ? enx[v] : sc::NOENT;
+            enx[v] = q < n ? sp.colmap[(k + 1) * n + q] : sc::NOENT;
+        }
+        const double zk = rd_pos<VPL>(z, k);
+#pragma unroll
+        for (int v = 0; v < VPL; ++v)
+            if (e[v] != sc::NOENT) z[v] = fma(-E[e[v]], zk, z[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int q = lane + 64 * v;
+        if (q < n) z[v] *= DINV[q];
+    }
+    // backward with the unit-diagonal U: x_i -= u'_ik x_k, k descending
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int q = lane + 64 * v;
+        enx[v] = q < n ? sp.colmap[(n - 1) * n + q] : sc::NOENT;
+    }
+    for (int k = n - 1; k > 0; --k) {
+        uint16_t e[VPL];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+            const int q = lane + 64 * v;
+            e[v] = q < k ? enx[v] : sc::NOENT;
+            enx[v] = q < n ? sp.colmap[(k - 1) * n + q] : sc::NOENT;
+        }
+        const double zk = rd_pos<VPL>(z, k);
+#pragma unroll
+        for (int v = 0; v < VPL; ++v)
+            if (e[v] != sc::NOENT) z[v] = fma(-E[e[v]], zk, z[v]);
+    }
+    __syncthreads();  // every lane has read X
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        const int q = lane + 64 * v;
+        if (q < n) X[q] = z[v];
+    }
     __syncthreads();
-    sweep(E, X, sp.bw_lvl, sp.bw, sp.nl_bw, lane);
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
         const int c = lane + 64 * v;
@@ -516,8 +624,12 @@ __device__ void integrate_cell_v(const DevMech &m, const DevSparse &sp, const Op
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
+// (capping the registers for two waves per SIMD, which the LDS of a
+// 53-species cell would allow, spills 78-117 registers to scratch: one wave
+// per SIMD it is)
+#define SP_OCC
 template <int VPL, bool CV>
-__global__ void __launch_bounds__(WAVE) k_integrate_sp(DevMech mk, DevSparse sp, Opts o, int64_t n,
+__global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp(DevMech mk, DevSparse sp, Opts o, int64_t n,
                                                        const double *T0, const double *P, const double *Y0,
                                                        int64_t ld, const double *DT, const double *dlnA,
                                                        double *h_io, double *T1, double *Y1, int32_t *status,
@@ -531,7 +643,7 @@ __global__ void __launch_bounds__(WAVE) k_integrate_sp(DevMech mk, DevSparse sp,
 }
 
 template <int VPL, bool CV>
-__global__ void __launch_bounds__(WAVE) k_integrate_sp_persistent(DevMech mk, DevSparse sp, Opts o, int64_t n,
+__global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_persistent(DevMech mk, DevSparse sp, Opts o, int64_t n,
                                                                   const double *T0, const double *P,
                                                                   const double *Y0, int64_t ld, const double *DT,
                                                                   const double *dlnA, double *h_io, double *T1,
@@ -559,7 +671,7 @@ __global__ void __launch_bounds__(WAVE) k_integrate_sp_persistent(DevMech mk, De
 }
 
 template <int VPL, bool CV>
-__global__ void __launch_bounds__(WAVE) k_integrate_sp_static(DevMech mk, DevSparse sp, Opts o, int64_t n,
+__global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_static(DevMech mk, DevSparse sp, Opts o, int64_t n,
                                                               const double *T0, const double *P, const double *Y0,
                                                               int64_t ld, const double *DT, const double *dlnA,
                                                               double *h_io, double *T1, double *Y1,

@@ -50,22 +50,22 @@ def fixed_map(o, y0, p, dt, h, dlnA=None):
             return y
 
 
-def fd_gradient(o, y0, p, dt, h, w, dlnA, par_dirs):
+def fd_gradient(o, y0, p, dt, h, w, dlnA, par_dirs, scale=1.0):
     """Central differences of <w, map(y0, dlnA)>: one entry per state
     component (step 1e-6 |T| for T, 1e-6 max(|Y_k|, 1e-3) for Y_k: the
     floor keeps the cancellation error of trace species below 1e-6 of the
     map's size, and the map is smooth through Y_k = 0) and one per
-    rate-multiplier direction (step 1e-5)."""
+    rate-multiplier direction (step 1e-5); every step times `scale`."""
     n = y0.size
     g = np.empty(n)
     for k in range(n):
-        e = 1e-6 * (abs(y0[k]) if k == n - 1 else max(abs(y0[k]), 1e-3))
+        e = scale * 1e-6 * (abs(y0[k]) if k == n - 1 else max(abs(y0[k]), 1e-3))
         yp, ym = y0.copy(), y0.copy()
         yp[k] += e
         ym[k] -= e
         g[k] = (w @ fixed_map(o, yp, p, dt, h, dlnA) - w @ fixed_map(o, ym, p, dt, h, dlnA)) / (2 * e)
     gp = np.empty(len(par_dirs))
     for q, d in enumerate(par_dirs):
-        e = 1e-5
+        e = scale * 1e-5
         gp[q] = (w @ fixed_map(o, y0, p, dt, h, dlnA + e * d) - w @ fixed_map(o, y0, p, dt, h, dlnA - e * d)) / (2 * e)
     return g, gp

@@ -186,6 +186,84 @@ def test_adjoint_fixed_steps_chon53(torch, sc, oracle_mod):
     _fixed_case(torch, sc, oracle_mod, "C2", idx, 6, 0.1, npar=4, rel=1e-4)
 
 
+def test_adjoint_fixed_steps_stratified_c4(torch, sc):
+    """66 cells of the gradient workload (22 per class), six fixed steps
+    over dt/10: the device map equals the CPU map to 1e-8 and the discrete
+    adjoint (all 54 initial-state components and four rate-multiplier
+    directions) equals the stored central differences of that map
+    (tests/golden/c4_fd.npz) to 1e-4 relative, floored at 1e-3 of the
+    largest entry (the differences' own noise reaches ~1e-5 on the trace
+    species of hot equilibrated cells)."""
+    gz = np.load(os.path.join(HERE, "golden", "c4_fd.npz"))
+    # cells with a converged central-difference reference: the differences at
+    # the stored steps and at half of them agree to 1e-5 (floored as below)
+    full = np.concatenate([gz["g"], gz["gp"]], 1)
+    half = np.concatenate([gz["g_half"], gz["gp_half"]], 1)
+    with np.errstate(invalid="ignore"):
+        dref = np.maximum(np.abs(full), 1e-3 * np.abs(full).max(1, keepdims=True))
+        ok = np.isfinite(full).all(1) & ((np.abs(full - half) / dref).max(1) <= 1e-5)
+    print(f"{ok.sum()} of {ok.size} cells have converged central differences")
+    assert ok.sum() >= 40, ok.sum()  # 44 of the stored 66 (the rest: stiff near-ignition cells)
+    g = {k: (gz[k][ok] if gz[k].ndim and gz[k].shape[0] == ok.size else gz[k]) for k in gz.files}
+    c = cells("C4")
+    mech = c["mech"]
+    idx = g["idx"]
+    nsteps = int(g["nsteps"])
+    plan = sc.Plan(sc.Mechanism(mech.to_text()), fixed_step=True, max_steps=1000)
+    T, p, Y, _ = state_gpu(torch, c, idx)
+    dt = dev(torch, g["dt"])
+    h = dt / nsteps
+    dlnA = g["dlnA"]
+    out = plan.integrate(T, p, Y, dt, dlnA=dlnA, h=h)
+    r = plan.adjoint(T, p, Y, dt, dev(torch, g["wT"]), dev(torch, g["wY"].T), dlnA=dlnA, h=h, per_cell=True)
+    assert np.all(r["status"].cpu().numpy() == 0) and np.all(out["status"].cpu().numpy() == 0)
+    y1 = np.concatenate([out["Y"].cpu().numpy().T, out["T"].cpu().numpy()[:, None]], 1)
+    scale = np.concatenate([np.maximum(np.abs(g["y1"][:, :-1]), 1e-8), np.abs(g["y1"][:, -1:])], 1)
+    worst_map = np.max(np.abs(y1 - g["y1"]) / scale)
+    got = np.concatenate([r["gY0"].cpu().numpy().T, r["gT0"].cpu().numpy()[:, None],
+                          (g["dirs"] @ r["g_dlnA_cell"].cpu().numpy()).T], 1)
+    ref = np.concatenate([g["g"], g["gp"]], 1)
+    den = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max(1, keepdims=True))
+    err = (np.abs(got - ref) / den).max(1)
+    for k in range(3):
+        print(f"class {k}: worst gradient error {err[g['cls'] == k].max():.3g}")
+    print(f"map {worst_map:.3g}, gradient {err.max():.3g} over {idx.size} cells")
+    assert worst_map < 1e-8, worst_map
+    assert err.max() < 1e-4, (err.max(), idx[np.argmax(err)])
+
+
+def test_adjoint_dot_product_linear(torch, sc):
+    """Dot-product test on a problem whose fixed-step map is exactly linear
+    in the mass fractions (the isomerisation A <=> B: equal molar masses and
+    enthalpies keep rho and T constant): for a perturbation dY of the
+    initial mass fractions, <lambda_N, Y_N(Y0 + dY) - Y_N(Y0)> equals
+    <lambda_0, dY> with lambda_0 the adjoint of lambda_N, to roundoff."""
+    from synth.mechgen import isomer_mechanism
+    mech = isomer_mechanism(log10A=9.0, b=0.0, Ea=40e3, ds_R=0.7)
+    plan = sc.Plan(sc.Mechanism(mech.to_text()), fixed_step=True, max_steps=1000)
+    rng = np.random.default_rng(9)
+    n = 32
+    T = np.full(n, 1000.0)
+    p = np.full(n, 101325.0)
+    Y0 = rng.dirichlet([1.0, 1.0], n)
+    dY = rng.normal(size=(n, 2)) * 1e-3
+    dt = np.full(n, 1e-2)
+    h = dt / rng.integers(3, 40, n)
+    lam = rng.normal(size=(n, 2))
+    a = plan.integrate(dev(torch, T), dev(torch, p), dev(torch, Y0.T), dev(torch, dt), h=dev(torch, h))
+    b = plan.integrate(dev(torch, T), dev(torch, p), dev(torch, (Y0 + dY).T), dev(torch, dt), h=dev(torch, h))
+    r = plan.adjoint(dev(torch, T), dev(torch, p), dev(torch, Y0.T), dev(torch, dt), dev(torch, np.zeros(n)),
+                     dev(torch, lam.T), h=dev(torch, h))
+    lhs = np.sum(lam * (b["Y"].cpu().numpy().T - a["Y"].cpu().numpy().T), 1)
+    rhs = np.sum(r["gY0"].cpu().numpy().T * dY, 1)
+    # relative 1e-10, floored at the roundoff of the two forward maps
+    # (eps |lambda| |Y| per step and component)
+    floor = 1e-16 * np.sum(np.abs(lam), 1) * (dt / h)
+    assert np.all(np.abs(lhs - rhs) <= 1e-10 * np.abs(lhs) + floor), np.max(np.abs(lhs - rhs) / np.abs(lhs))
+    # and the temperature adjoint of this isothermal map is the chain through k(T): finite
+    assert np.all(np.isfinite(r["gT0"].cpu().numpy()))
+
+
 def test_adjoint_segment_recompute(torch, sc, oracle_mod):
     """2500 fixed steps: more than the 2048 checkpoint slots, so the recorder
     thins its checkpoints and the reverse sweep recomputes segments."""
