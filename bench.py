@@ -709,7 +709,16 @@ def bench_lts(args):
     tr_ms = [e[1].elapsed_time(e[2]) for e in ev]
     steps = (d.steps - steps0).cpu().numpy()
     failed = int(d.failed.sum())
-    flops = float(steps.sum()) * mech.info["flops_step"] / args.steps
+    flops = float(steps.sum()) * step_flops(mech.info, "ros4") / args.steps
+    # where the cells and the integrator steps are: by inflow stream row and
+    # by the settled local temperature
+    Tset = d.T.cpu().numpy()
+    zones = {"stream_jet": f["stream"] == 0, "stream_pilot": f["stream"] == 1, "stream_coflow": f["stream"] == 2,
+             "T_below_600K": Tset < 600.0, "T_600_1500K": (Tset >= 600.0) & (Tset < 1500.0),
+             "T_above_1500K": Tset >= 1500.0}
+    by_zone = {k: {"cells_share": float(z.mean()), "steps_share": float(steps[z].sum() / max(1, steps.sum())),
+                   "steps_per_cell_per_split_step": float(steps[z].mean() / args.steps) if z.any() else 0.0}
+               for k, z in zones.items()}
     chem_s = float(np.mean(chem_ms)) / 1e3
     achieved = flops / chem_s / 1e12
     tr_bytes = 2 * (N + 1) * n * 8 + 2 * n * 8 + (N + 1) * f["ny"] * 8
@@ -726,7 +735,7 @@ def bench_lts(args):
                        "transport_ms": float(np.mean(tr_ms)), "steps_per_cell_per_split_step": float(steps.mean()) / args.steps,
                        "failed_cells": failed, "max_abs_sum_Y_minus_1": ysum, "spinup_steps": args.spinup,
                        "spinup_s": spin_s, "T_max": float(d.T.max()),
-                       "cells_above_1000K": int((d.T > 1000.0).sum())},
+                       "cells_above_1000K": int((d.T > 1000.0).sum()), "work_by_zone": by_zone},
             "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel_ms": chem_s * 1e3,
                          "flops_per_launch": flops},

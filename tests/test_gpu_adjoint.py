@@ -236,8 +236,9 @@ def test_adjoint_dot_product_linear(torch, sc):
     """Dot-product test on a problem whose fixed-step map is exactly linear
     in the mass fractions (the isomerisation A <=> B: equal molar masses and
     enthalpies keep rho and T constant): for a perturbation dY of the
-    initial mass fractions, <lambda_N, Y_N(Y0 + dY) - Y_N(Y0)> equals
-    <lambda_0, dY> with lambda_0 the adjoint of lambda_N, to roundoff."""
+    initial mass fractions (between two valid states), <lambda_N,
+    Y_N(Y0 + dY) - Y_N(Y0)> equals <lambda_0, dY> with lambda_0 the adjoint
+    of lambda_N, to roundoff."""
     from synth.mechgen import isomer_mechanism
     mech = isomer_mechanism(log10A=9.0, b=0.0, Ea=40e3, ds_R=0.7)
     plan = sc.Plan(sc.Mechanism(mech.to_text()), fixed_step=True, max_steps=1000)
@@ -246,7 +247,11 @@ def test_adjoint_dot_product_linear(torch, sc):
     T = np.full(n, 1000.0)
     p = np.full(n, 101325.0)
     Y0 = rng.dirichlet([1.0, 1.0], n)
-    dY = rng.normal(size=(n, 2)) * 1e-3
+    # a second valid state as the perturbation's end point: the map is linear,
+    # so the perturbation may be large, which keeps the difference of the two
+    # forward results clear of their cancellation (a 1e-3 perturbation loses
+    # three digits of it)
+    dY = rng.dirichlet([1.0, 1.0], n) - Y0
     dt = np.full(n, 1e-2)
     h = dt / rng.integers(3, 40, n)
     lam = rng.normal(size=(n, 2))
