@@ -252,7 +252,11 @@ def test_adjoint_dot_product_linear(torch, sc):
     # forward results clear of their cancellation (a 1e-3 perturbation loses
     # three digits of it)
     dY = rng.dirichlet([1.0, 1.0], n) - Y0
-    dt = np.full(n, 1e-2)
+    # (k_f + k_r) dt = 2.4: a perturbation of the composition has partly
+    # relaxed (a longer dt would leave only the equilibrium, which a
+    # zero-sum perturbation does not move, and the check would compare
+    # roundoff with roundoff)
+    dt = np.full(n, 2e-7)
     h = dt / rng.integers(3, 40, n)
     lam = rng.normal(size=(n, 2))
     a = plan.integrate(dev(torch, T), dev(torch, p), dev(torch, Y0.T), dev(torch, dt), h=dev(torch, h))
