@@ -175,7 +175,10 @@ sc_status sc_species_index(const sc_mech *mech, const char *name, int32_t *idx);
  *   "perm" (int32: position -> variable; species 0..N-1, N = T, N+1 = the
  *     border unknown sigma), "pattern" (uint8, N*N species-term pattern),
  *   "apat" (uint8, (N+2)^2 bordered pattern in positions),
- *   "erow", "ecol" (int32: row and column position of each L+U entry),
+ *   "erow", "ecol" (int32: row and column position of each L+U entry;
+ *     entries are numbered column by column, rows ascending),
+ *   "cstart" (int32, n + 1: first entry of each column), "cmask" (uint64,
+ *     2 per column: bit i of word i / 64 set when row i has an entry),
  *   "lu_b_lvl", "lu_c_lvl", "fw_lvl", "bw_lvl", "tfw_lvl", "tbw_lvl" (int32
  *     level offsets), "lu_b", "lu_u", "diag" (uint32 items), "lu_c", "fw",
  *     "bw", "tfw", "tbw" (uint64 items), "rxi" (uint16, RXI entries per
@@ -241,6 +244,50 @@ sc_status sc_integrate_noalloc(sc_plan *plan, int64_t n, const double *T0, const
                                int64_t ld, const double *dt, const double *dlnA, double *h_io, double *T1,
                                double *Y1, int32_t *cell_status, int32_t *n_acc, int32_t *n_rej,
                                void *hip_stream);
+
+/* Zonal reference-cell mapping (paper Sec. 2.5: the load-balanced solver the
+ * paper builds on maps the chemistry solution of low-reactivity regions from
+ * a reference cell instead of integrating every cell).  Low reactivity is a
+ * mixture fraction below z_tol: Z = (beta - beta_ox) / (beta_fuel - beta_ox)
+ * with Bilger's coupling function beta = sum_k (2 n_C,k + n_H,k / 2 -
+ * n_O,k) Y_k / W_k (element atoms per species k; other elements do not
+ * count), evaluated for the cell and for the two streams.  Zones are bands
+ * of temperature of width dT (floor(T / dT) < ceil(SC_MAP_T_MAX / dT)) and,
+ * when dlnp > 0, bands of ln(p / 1 Pa) of width dlnp (0 <= floor(ln p /
+ * dlnp) < ceil(ln SC_MAP_P_MAX / dlnp)). */
+#define SC_MAP_T_MAX 10000.0
+#define SC_MAP_P_MAX 1e9
+typedef struct {
+    double z_tol; /* cells with Z < z_tol are mapped (finite) */
+    double dT;    /* temperature band width [K], > 0 */
+    double dlnp;  /* ln p band width, >= 0 (0: one band for every pressure) */
+} sc_mapping;
+
+/* Set the plan's mapping: the fuel and oxidiser stream compositions
+ * (HOST arrays of N mass fractions) and the options above.  Allocates the
+ * plan's zone table (64 MiB) on the first call.  SC_EINVAL for non-finite
+ * or out-of-range options, streams with equal beta, or more than 2^24
+ * zones. */
+sc_status sc_plan_set_mapping(sc_plan *plan, const double *Y_fuel, const double *Y_ox, const sc_mapping *opt);
+
+/* sc_integrate with the plan's mapping (set by sc_plan_set_mapping): a
+ * mappable cell whose zone holds a mappable cell of lower index is not
+ * integrated; the zone's lowest-index cell (its reference) is, and each
+ * other cell of the zone takes the reference's change over the step scaled
+ * by the ratio of the steps, as a mean rate:
+ *   T1 = T0 + (T1_ref - T0_ref) dt / dt_ref, Y1 likewise per species,
+ * with the reference's status and zero step counts (h_io is left as it
+ * was).  Mapped cells need finite inputs and T, p, dt > 0.
+ *   out: ref[n] (device): the reference of every cell (c itself when the
+ *        cell was integrated), plus the sc_integrate outputs.
+ * T1 and Y1 must not alias T0 and Y0 (SC_EINVAL).  The classification is a
+ * few passes over the batch before the integration and one after it, on the
+ * same stream; the launch options of the plan apply to the integrated
+ * cells (the skipped ones cost a queue pull each). */
+sc_status sc_integrate_mapped(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0,
+                              int64_t ld, const double *dt, const double *dlnA, double *h_io, double *T1,
+                              double *Y1, int32_t *cell_status, int32_t *n_acc, int32_t *n_rej, int32_t *ref,
+                              void *hip_stream);
 
 /* Vector-Jacobian product of the right-hand side (the transpose of the
  * sc_jacobian matrix applied to a weight): for every cell

@@ -42,6 +42,10 @@ class Options(C.Structure):
                 ("reactor", C.c_int32), ("method", C.c_int32), ("linalg", C.c_int32)]
 
 
+class Mapping(C.Structure):
+    _fields_ = [("z_tol", C.c_double), ("dT", C.c_double), ("dlnp", C.c_double)]
+
+
 class MechInfo(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n_species", "n_reactions", "n_third_body", "n_troe",
                                          "n_elements", "n_state", "n_padded", "nnz_jac", "nnz_lu",
@@ -82,6 +86,8 @@ def lib():
         L.sc_linsolve.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P]
         L.sc_integrate.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
         L.sc_integrate_noalloc.argtypes = L.sc_integrate.argtypes
+        L.sc_plan_set_mapping.argtypes = [_P, _P, _P, C.POINTER(Mapping)]
+        L.sc_integrate_mapped.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
         L.sc_vjp.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]
         L.sc_adjoint.argtypes = [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                  _P, _P, _P, _P, C.c_size_t, C.POINTER(C.c_size_t), _P]
@@ -91,7 +97,8 @@ def lib():
         L.sc_adjoint_slot_bytes.argtypes = [_P]
         L.sc_adjoint_slot_bytes.restype = C.c_size_t
         for f in ("sc_mech_load", "sc_mech_info_get", "sc_species_index", "sc_plan_create", "sc_rhs",
-                  "sc_jacobian", "sc_linsolve", "sc_integrate", "sc_integrate_noalloc", "sc_vjp", "sc_adjoint"):
+                  "sc_jacobian", "sc_linsolve", "sc_integrate", "sc_integrate_noalloc", "sc_vjp", "sc_adjoint",
+                  "sc_plan_set_mapping", "sc_integrate_mapped"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -296,6 +303,40 @@ class Plan:
         _check(getattr(lib(), _entry)(self._h, n, _ptr(T0), _ptr(p), _ptr(Y0), n, _ptr(dt), _ptr(d),
                                       _ptr(hio), _ptr(out["T"]), _ptr(out["Y"]), _ptr(out["status"]),
                                       _ptr(out["n_acc"]), _ptr(out["n_rej"]), _stream(t, self.device)))
+        if hio is not None:
+            out["h"] = hio
+        return out
+
+    def set_mapping(self, Y_fuel, Y_ox, z_tol, dT, dlnp=0.0):
+        """Zonal reference-cell mapping for integrate_mapped(): fuel and
+        oxidiser stream mass fractions (N each), the mixture-fraction bound
+        z_tol, the temperature band dT [K] and the ln p band dlnp (0: none)."""
+        import numpy as np
+        N = self.mech.N
+        yf = np.ascontiguousarray(Y_fuel, dtype=np.float64)
+        yo = np.ascontiguousarray(Y_ox, dtype=np.float64)
+        if yf.shape != (N,) or yo.shape != (N,):
+            raise ValueError(f"stream compositions must have {N} mass fractions")
+        opt = Mapping(float(z_tol), float(dT), float(dlnp))
+        _check(lib().sc_plan_set_mapping(self._h, yf.ctypes.data, yo.ctypes.data, C.byref(opt)))
+
+    def integrate_mapped(self, T0, p, Y0, dt, dlnA=None, h=None, out=None):
+        """integrate() with the mapping of set_mapping(): returns the same dict
+        plus ref [n] (int32), each cell's reference (itself when integrated)."""
+        T0, p, Y0, n = self._state(T0, p, Y0)
+        dt = self._cells(dt, n, "dt")
+        d = self._dlnA(dlnA)
+        hio = None if h is None else self._cells(h, n, "h").clone()
+        t = self.torch
+        dev = T0.device
+        if out is None:
+            out = dict(T=t.empty_like(T0), Y=t.empty_like(Y0), status=t.empty(n, dtype=t.int32, device=dev),
+                       n_acc=t.zeros(n, dtype=t.int32, device=dev), n_rej=t.zeros(n, dtype=t.int32, device=dev))
+        if "ref" not in out:
+            out["ref"] = t.empty(n, dtype=t.int32, device=dev)
+        _check(lib().sc_integrate_mapped(self._h, n, _ptr(T0), _ptr(p), _ptr(Y0), n, _ptr(dt), _ptr(d), _ptr(hio),
+                                         _ptr(out["T"]), _ptr(out["Y"]), _ptr(out["status"]), _ptr(out["n_acc"]),
+                                         _ptr(out["n_rej"]), _ptr(out["ref"]), _stream(t, self.device)))
         if hio is not None:
             out["h"] = hio
         return out

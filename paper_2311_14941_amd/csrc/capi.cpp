@@ -37,6 +37,8 @@ struct sc_plan {
     size_t adj_ws_bytes = 0;
     void *gcell_ws = nullptr;    // per-cell parameter adjoints when the caller passes none
     size_t gcell_ws_bytes = 0;
+    bool mapping = false;        // sc_plan_set_mapping has been called
+    scdev::MapParams mp{};       // its weights and zone table (device), band sizes
 };
 
 namespace {
@@ -230,6 +232,8 @@ sc_status sc_mech_sparse_array(const sc_mech *mech, const char *name, void *out,
     else if (k == "tfw") take(s.tfw);
     else if (k == "tbw") take(s.tbw);
     else if (k == "rxi") take(s.rxi);
+    else if (k == "cstart") take(s.cstart);
+    else if (k == "cmask") take(s.cmask);
     else return fail(SC_EINVAL, "unknown sparse array " + k);
     if (out && sz) std::memcpy(out, src, std::min(sz, *bytes));
     *bytes = sz;
@@ -277,8 +281,10 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
                                          " species; use the sparse one (linalg = SC_LINALG_SPARSE or AUTO)");
     if (sparse && o.method != SC_METHOD_ROS4)
         return fail(SC_EUNSUPPORTED, "the extrapolation baseline runs with the dense linear algebra only");
-    const int vpl = nstate <= 64 ? 1 : 2;
     const sc::SparseLU &S = mech->m.sp;
+    // the sparse kernels' vectors hold every position of the bordered
+    // system (N + 2 of them) in one or two slots per lane
+    const int vpl = S.n <= 64 ? 1 : 2;
     scdev::DevSparse ds{};
     if (sparse) {
         const int NV = 64 * vpl;
@@ -399,17 +405,16 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
         comp[(size_t)scdev::CMP * N] = S.pos[N];
         comp[(size_t)scdev::CMP * N + 1] = S.e_TT;
         comp[(size_t)scdev::CMP * N + 2] = S.e_SS;
-        std::vector<uint16_t> emap(S.emap.size()), colmap(S.emap.size());
+        std::vector<uint16_t> emap(S.emap.size());
         for (size_t i = 0; i < emap.size(); ++i) emap[i] = S.emap[i] < 0 ? sc::NOENT : (uint16_t)S.emap[i];
-        for (int r = 0; r < S.n; ++r)
-            for (int k = 0; k < S.n; ++k) colmap[(size_t)k * S.n + r] = emap[(size_t)r * S.n + k];
         scdev::DevSparse &q = p->ds;
         std::vector<uint64_t> lu_b(S.lu_b.begin(), S.lu_b.end());
         ok = upload(p, S.lu_b_lvl, &q.lu_b_lvl) && upload(p, S.lu_c_lvl, &q.lu_c_lvl) &&
              upload(p, S.fw_lvl, &q.fw_lvl) && upload(p, S.bw_lvl, &q.bw_lvl) && upload(p, lu_b, &q.lu_b) &&
              upload(p, S.lu_u, &q.lu_u) && upload(p, S.diag, &q.diag) && upload(p, S.lu_c, &q.lu_c) &&
              upload(p, S.fw, &q.fw) && upload(p, S.bw, &q.bw) && upload(p, rxi, &q.rxi) &&
-             upload(p, comp, &q.comp) && upload(p, emap, &q.emap) && upload(p, colmap, &q.colmap);
+             upload(p, comp, &q.comp) && upload(p, emap, &q.emap) && upload(p, S.cstart, &q.cstart) &&
+             upload(p, S.cmask, &q.cmask);
     }
     if (ok) {
         void *q = nullptr;
@@ -479,9 +484,12 @@ sc_status sc_linsolve(sc_plan *plan, int64_t n, const double *T, const double *p
 // sc_integrate and its allocation-free variant: with `noalloc` the queue
 // counter and the ordering workspace come from the library's fixed device
 // scratch instead of the plan's allocations.
+// With `ref`, the cells whose ref is another cell are skipped (mapped
+// afterwards by the caller).
 static sc_status integrate_impl(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0, int64_t ld,
                          const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
-                         int32_t *cell_status, int32_t *n_acc, int32_t *n_rej, void *stream, bool noalloc)
+                         int32_t *cell_status, int32_t *n_acc, int32_t *n_rej, void *stream, bool noalloc,
+                         const int32_t *ref = nullptr)
 {
     sc_status s = check_common(plan, n, ld, {T0, p, Y0, dt, T1, Y1, cell_status});
     if (s != SC_OK || n == 0) return s;
@@ -535,27 +543,27 @@ static sc_status integrate_impl(sc_plan *plan, int64_t n, const double *T0, cons
         if (e == hipSuccess && plan->sparse)
             e = scdev::launch_integrate_sp_persistent(plan->vpl, plan->dm, plan->ds, o, n, T0, p, Y0, ld, dt, dlnA,
                                                       h_io, T1, Y1, cell_status, n_acc, n_rej, queue, perm, tile,
-                                                      grid, st);
+                                                      grid, ref, st);
         else if (e == hipSuccess)
             e = scdev::launch_integrate_persistent(plan->np, plan->dm, o, plan->opt.method, n, T0, p, Y0, ld, dt,
                                                    dlnA, h_io, T1, Y1, cell_status, n_acc, n_rej, queue, perm, tile,
-                                                   grid, st);
+                                                   grid, ref, st);
     } else if (plan->opt.mode == SC_MODE_STATIC) {
         int grid = plan->opt.grid > 0 ? plan->opt.grid : plan->capacity;
         if (grid <= 0) grid = 1;
         if (grid > n) grid = (int)n;
         if (plan->sparse)
             e = scdev::launch_integrate_sp_static(plan->vpl, plan->dm, plan->ds, o, n, T0, p, Y0, ld, dt, dlnA, h_io,
-                                                  T1, Y1, cell_status, n_acc, n_rej, grid, st);
+                                                  T1, Y1, cell_status, n_acc, n_rej, grid, ref, st);
         else
             e = scdev::launch_integrate_static(plan->np, plan->dm, o, plan->opt.method, n, T0, p, Y0, ld, dt, dlnA,
-                                               h_io, T1, Y1, cell_status, n_acc, n_rej, grid, st);
+                                               h_io, T1, Y1, cell_status, n_acc, n_rej, grid, ref, st);
     } else if (plan->sparse) {
         e = scdev::launch_integrate_sp(plan->vpl, plan->dm, plan->ds, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1,
-                                       cell_status, n_acc, n_rej, st);
+                                       cell_status, n_acc, n_rej, ref, st);
     } else {
         e = scdev::launch_integrate(plan->np, plan->dm, o, plan->opt.method, n, T0, p, Y0, ld, dt, dlnA, h_io, T1,
-                                    Y1, cell_status, n_acc, n_rej, st);
+                                    Y1, cell_status, n_acc, n_rej, ref, st);
     }
     return e == hipSuccess ? SC_OK : hip_fail(e, "integrate launch");
 }
@@ -572,6 +580,86 @@ sc_status sc_integrate_noalloc(sc_plan *plan, int64_t n, const double *T0, const
                                double *Y1, int32_t *cell_status, int32_t *n_acc, int32_t *n_rej, void *stream)
 {
     return integrate_impl(plan, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, cell_status, n_acc, n_rej, stream, true);
+}
+
+sc_status sc_plan_set_mapping(sc_plan *plan, const double *Y_fuel, const double *Y_ox, const sc_mapping *opt)
+{
+    if (!plan || !Y_fuel || !Y_ox || !opt) return fail(SC_EINVAL, "NULL argument");
+    const sc::Mech &m = plan->m;
+    const int N = m.N;
+    if (!std::isfinite(opt->z_tol)) return fail(SC_EINVAL, "z_tol must be finite");
+    if (!(opt->dT > 0.0) || !std::isfinite(opt->dT)) return fail(SC_EINVAL, "dT must be positive");
+    if (!(opt->dlnp >= 0.0) || !std::isfinite(opt->dlnp)) return fail(SC_EINVAL, "dlnp must be >= 0");
+    for (int k = 0; k < N; ++k)
+        if (!std::isfinite(Y_fuel[k]) || !std::isfinite(Y_ox[k]))
+            return fail(SC_EINVAL, "stream compositions must be finite");
+    // Bilger's coupling function per unit mass: carbon 2, hydrogen 1/2,
+    // oxygen -1 mole per mole of atoms; other elements do not count
+    std::vector<double> w(N, 0.0);
+    for (int e = 0; e < m.E; ++e) {
+        const std::string &el = m.elements[e];
+        const double a = el == "C" ? 2.0 : el == "H" ? 0.5 : el == "O" ? -1.0 : 0.0;
+        if (a != 0.0)
+            for (int k = 0; k < N; ++k) w[k] += a * m.comp[(size_t)k * m.E + e];
+    }
+    for (int k = 0; k < N; ++k) w[k] /= m.W[k];
+    double bf = 0.0, bo = 0.0;
+    for (int k = 0; k < N; ++k) {
+        const double tf = w[k] * Y_fuel[k];
+        bf = bf + tf;
+        const double to = w[k] * Y_ox[k];
+        bo = bo + to;
+    }
+    if (!(bf != bo) || !std::isfinite(bf - bo))
+        return fail(SC_EINVAL, "fuel and oxidiser streams have the same coupling function");
+    const double nT = std::ceil(SC_MAP_T_MAX / opt->dT);
+    const double np = opt->dlnp > 0.0 ? std::ceil(std::log(SC_MAP_P_MAX) / opt->dlnp) : 1.0;
+    if (nT * np > (double)(1 << 24))
+        return fail(SC_EINVAL, "dT and dlnp give more than 2^24 zones");
+    DeviceGuard g(plan->device);
+    if (!plan->mapping) {
+        // weights and the largest table, allocated once per plan
+        void *dw = nullptr, *dt = nullptr;
+        if (hipMalloc(&dw, sizeof(double) * (size_t)N) != hipSuccess) return fail(SC_ENOMEM, "mapping weights");
+        plan->allocs.push_back(dw);
+        if (hipMalloc(&dt, sizeof(int32_t) << 24) != hipSuccess) return fail(SC_ENOMEM, "mapping zone table");
+        plan->allocs.push_back(dt);
+        plan->mp.w = static_cast<const double *>(dw);
+        plan->mp.table = static_cast<int32_t *>(dt);
+    }
+    if (hipMemcpy(const_cast<double *>(plan->mp.w), w.data(), sizeof(double) * (size_t)N, hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return fail(SC_EHIP, "mapping weights upload");
+    plan->mp.beta_ox = bo;
+    plan->mp.dbeta = bf - bo;
+    plan->mp.z_tol = opt->z_tol;
+    plan->mp.dT = opt->dT;
+    plan->mp.dlnp = opt->dlnp;
+    plan->mp.nT = (int)nT;
+    plan->mp.np = (int)np;
+    plan->mapping = true;
+    return SC_OK;
+}
+
+sc_status sc_integrate_mapped(sc_plan *plan, int64_t n, const double *T0, const double *p, const double *Y0,
+                              int64_t ld, const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
+                              int32_t *cell_status, int32_t *n_acc, int32_t *n_rej, int32_t *ref, void *stream)
+{
+    sc_status s = check_common(plan, n, ld, {T0, p, Y0, dt, T1, Y1, cell_status, ref});
+    if (s != SC_OK) return s;
+    if (!plan->mapping) return fail(SC_EINVAL, "sc_plan_set_mapping has not been called on this plan");
+    if (T1 == T0 || Y1 == Y0)
+        return fail(SC_EINVAL, "the mapped integration needs T1, Y1 apart from T0, Y0 (mapped cells add the "
+                               "reference's change to their inputs)");
+    if (n == 0) return SC_OK;
+    DeviceGuard g(plan->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = scdev::launch_map_classify(plan->mp, plan->m.N, n, T0, p, Y0, ld, dt, ref, st);
+    if (e != hipSuccess) return hip_fail(e, "mapping classification");
+    s = integrate_impl(plan, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, cell_status, n_acc, n_rej, stream, false, ref);
+    if (s != SC_OK) return s;
+    e = scdev::launch_map_apply(plan->m.N, n, ref, T0, Y0, ld, dt, T1, Y1, cell_status, n_acc, n_rej, st);
+    return e == hipSuccess ? SC_OK : hip_fail(e, "mapping");
 }
 
 sc_status sc_vjp(sc_plan *plan, int64_t n, const double *T, const double *p, const double *Y, int64_t ld,

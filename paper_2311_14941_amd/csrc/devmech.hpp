@@ -60,7 +60,8 @@ struct DevSparse {
     const uint16_t *rxi;   // [R][RXI_SIZE], reaction execution order
     const int32_t *comp;   // per species k: pos, e_kk, e_kT, e_kS, e_Tk, e_Sk; then pos_T, e_TT, e_SS
     const uint16_t *emap;    // n * n: (row, column) position -> entry or NOENT, row-major
-    const uint16_t *colmap;  // the same map column-major: colmap[k * n + i] = entry of (i, k)
+    const int32_t *cstart;   // n + 1: first entry of each column (entries are numbered column by column)
+    const uint64_t *cmask;   // 2 n: rows with an entry in column k, lanes 0-63 then 64-127
 };
 constexpr int CMP = 6;  // comp entries per species
 
@@ -81,16 +82,16 @@ hipError_t launch_linsolve(int np, const DevMech &m, int64_t n, const double *T,
 hipError_t launch_integrate(int np, const DevMech &m, const Opts &o, int method, int64_t n,
                             const double *T0, const double *p, const double *Y0, int64_t ld, const double *dt,
                             const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na,
-                            int32_t *nr, hipStream_t s);
+                            int32_t *nr, const int32_t *ref, hipStream_t s);
 hipError_t launch_integrate_persistent(int np, const DevMech &m, const Opts &o, int method, int64_t n,
                                        const double *T0, const double *p, const double *Y0, int64_t ld,
                                        const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
                                        int32_t *st, int32_t *na, int32_t *nr, unsigned long long *queue,
-                                       const int32_t *perm, int tile, int grid, hipStream_t s);
+                                       const int32_t *perm, int tile, int grid, const int32_t *ref, hipStream_t s);
 hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int method, int64_t n,
                                    const double *T0, const double *p, const double *Y0, int64_t ld, const double *dt,
                                    const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st,
-                                   int32_t *na, int32_t *nr, int grid, hipStream_t s);
+                                   int32_t *na, int32_t *nr, int grid, const int32_t *ref, hipStream_t s);
 hipError_t order_cells(int order, int64_t n, const double *dt, const int32_t *na, const int32_t *nr,
                        void **ws, size_t *ws_bytes, int32_t **perm, hipStream_t s);
 hipError_t order_ws_need(int order, int64_t n, size_t *need, hipStream_t s);
@@ -115,18 +116,36 @@ hipError_t launch_linsolve_sp(int vpl, const DevMech &m, const DevSparse &sp, in
 hipError_t launch_integrate_sp(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o, int64_t n,
                                const double *T0, const double *p, const double *Y0, int64_t ld, const double *dt,
                                const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na,
-                               int32_t *nr, hipStream_t s);
+                               int32_t *nr, const int32_t *ref, hipStream_t s);
 hipError_t launch_integrate_sp_persistent(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o,
                                           int64_t n, const double *T0, const double *p, const double *Y0,
                                           int64_t ld, const double *dt, const double *dlnA, double *h_io,
                                           double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr,
                                           unsigned long long *queue, const int32_t *perm, int tile, int grid,
-                                          hipStream_t s);
+                                          const int32_t *ref, hipStream_t s);
 hipError_t launch_integrate_sp_static(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o, int64_t n,
                                       const double *T0, const double *p, const double *Y0, int64_t ld,
                                       const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
-                                      int32_t *st, int32_t *na, int32_t *nr, int grid, hipStream_t s);
+                                      int32_t *st, int32_t *na, int32_t *nr, int grid, const int32_t *ref,
+                                      hipStream_t s);
 int persistent_capacity_sp(int vpl, const DevSparse &sp, int device);
+
+// zonal reference-cell mapping (mapping.hip): the zone table is cleared,
+// every mappable cell claims its zone (lowest index wins) and gets its
+// reference in ref (ref[c] = c for cells that are integrated); after the
+// integration, apply writes the mapped cells from their references
+struct MapParams {
+    const double *w;     // N per-species weights of Bilger's coupling function
+    double beta_ox, dbeta, z_tol;  // dbeta = beta_fuel - beta_ox
+    double dT, dlnp;     // band widths (dlnp = 0: no pressure bands)
+    int nT, np;          // band counts; the table holds nT * np zones
+    int32_t *table;      // nT * np zone claims
+};
+hipError_t launch_map_classify(const MapParams &mp, int N, int64_t n, const double *T, const double *p,
+                               const double *Y, int64_t ld, const double *dt, int32_t *ref, hipStream_t s);
+hipError_t launch_map_apply(int N, int64_t n, const int32_t *ref, const double *T0, const double *Y0, int64_t ld,
+                            const double *dt, double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr,
+                            hipStream_t s);
 
 // adjoint (adjoint.hip)
 hipError_t launch_vjp(int np, const DevMech &m, int64_t n, const double *T, const double *p, const double *Y,

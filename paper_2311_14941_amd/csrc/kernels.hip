@@ -78,8 +78,10 @@ template <int NP, int METH>
 __device__ void integrate_cell(const DevMech &m, const Opts &o, double *lds, int64_t c, int lane, const double *T0,
                                const double *P, const double *Y0, int64_t ld, const double *DT, const double *dlnA,
                                double *h_io, double *T1, double *Y1, int32_t *status, int32_t *nacc_out,
-                               int32_t *nrej_out)
+                               int32_t *nrej_out, const int32_t *ref)
 {
+    // a cell mapped onto another cell's result is left to the mapping pass
+    if (ref && ref[c] != c) return;
     const int N = m.N;
     double y = load_state(m, T0, Y0, ld, c, lane);
     const double p = P[c], dt = DT[c];
@@ -104,13 +106,14 @@ template <int NP, bool CV, int METH>
 __global__ void __launch_bounds__(WAVE) k_integrate(DevMech mk, Opts o, int64_t n, const double *T0, const double *P,
                                                     const double *Y0, int64_t ld, const double *DT,
                                                     const double *dlnA, double *h_io, double *T1, double *Y1,
-                                                    int32_t *status, int32_t *nacc, int32_t *nrej)
+                                                    int32_t *status, int32_t *nacc, int32_t *nrej,
+                                                    const int32_t *ref)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
     const int64_t c = blockIdx.x;
     if (c >= n) return;
-    integrate_cell<NP, METH>(m, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
+    integrate_cell<NP, METH>(m, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej, ref);
 }
 
 // Persistent variant: a resident grid; each wave pulls tiles of `tile` cells
@@ -124,7 +127,7 @@ __global__ void __launch_bounds__(WAVE) k_integrate_persistent(DevMech mk, Opts 
                                                                double *T1, double *Y1, int32_t *status,
                                                                int32_t *nacc, int32_t *nrej,
                                                                unsigned long long *queue, const int32_t *perm,
-                                                               int tile)
+                                                               int tile, const int32_t *ref)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
@@ -139,7 +142,7 @@ __global__ void __launch_bounds__(WAVE) k_integrate_persistent(DevMech mk, Opts 
 #pragma unroll 1
         for (int64_t i = (int64_t)base; i < end; ++i) {
             const int64_t c = perm ? (int64_t)perm[i] : i;
-            integrate_cell<NP, METH>(m, o, lds, c, lane, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
+            integrate_cell<NP, METH>(m, o, lds, c, lane, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej, ref);
         }
     }
 }
@@ -151,7 +154,7 @@ __global__ void __launch_bounds__(WAVE) k_integrate_static(DevMech mk, Opts o, i
                                                            const double *P, const double *Y0, int64_t ld,
                                                            const double *DT, const double *dlnA, double *h_io,
                                                            double *T1, double *Y1, int32_t *status, int32_t *nacc,
-                                                           int32_t *nrej, int64_t group)
+                                                           int32_t *nrej, int64_t group, const int32_t *ref)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
@@ -159,7 +162,7 @@ __global__ void __launch_bounds__(WAVE) k_integrate_static(DevMech mk, Opts o, i
     const int64_t c1 = min(c0 + group, n);
 #pragma unroll 1
     for (int64_t c = c0; c < c1; ++c)
-        integrate_cell<NP, METH>(m, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
+        integrate_cell<NP, METH>(m, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej, ref);
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
@@ -249,10 +252,10 @@ hipError_t launch_linsolve(int np, const DevMech &m, int64_t n, const double *T,
 hipError_t launch_integrate(int np, const DevMech &m, const Opts &o, int method, int64_t n, const double *T0,
                             const double *p, const double *Y0, int64_t ld, const double *dt, const double *dlnA,
                             double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr,
-                            hipStream_t s)
+                            const int32_t *ref, hipStream_t s)
 {
     SC_DISPATCH_I(np, hipLaunchKernelGGL(SC_KERNEL_I(k_integrate), dim3((unsigned)n), dim3(WAVE), lds_bytes<NPV>(), s,
-                                         m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr));
+                                         m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, ref));
     return hipGetLastError();
 }
 
@@ -260,23 +263,23 @@ hipError_t launch_integrate_persistent(int np, const DevMech &m, const Opts &o, 
                                        const double *T0, const double *p, const double *Y0, int64_t ld,
                                        const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
                                        int32_t *st, int32_t *na, int32_t *nr, unsigned long long *queue,
-                                       const int32_t *perm, int tile, int grid, hipStream_t s)
+                                       const int32_t *perm, int tile, int grid, const int32_t *ref, hipStream_t s)
 {
     SC_DISPATCH_I(np, hipLaunchKernelGGL(SC_KERNEL_I(k_integrate_persistent), dim3((unsigned)grid), dim3(WAVE),
                                          lds_bytes<NPV>(), s, m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na,
-                                         nr, queue, perm, tile));
+                                         nr, queue, perm, tile, ref));
     return hipGetLastError();
 }
 
 hipError_t launch_integrate_static(int np, const DevMech &m, const Opts &o, int method, int64_t n,
                                    const double *T0, const double *p, const double *Y0, int64_t ld, const double *dt,
                                    const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st,
-                                   int32_t *na, int32_t *nr, int grid, hipStream_t s)
+                                   int32_t *na, int32_t *nr, int grid, const int32_t *ref, hipStream_t s)
 {
     const int64_t group = (n + grid - 1) / grid;
     const unsigned g = (unsigned)((n + group - 1) / group);
     SC_DISPATCH_I(np, hipLaunchKernelGGL(SC_KERNEL_I(k_integrate_static), dim3(g), dim3(WAVE), lds_bytes<NPV>(), s,
-                                         m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, group));
+                                         m, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, group, ref));
     return hipGetLastError();
 }
 

@@ -47,8 +47,10 @@ struct SparseLU {
     int n = 0, nnz = 0;
     std::vector<int> perm;        // position -> variable (species 0..N-1, N = T, N + 1 = sigma)
     std::vector<int> pos;         // variable -> position
-    std::vector<int> erow, ecol;  // entry -> (row position, column position), row-major order
+    std::vector<int> erow, ecol;  // entry -> (row position, column position), column-major order
     std::vector<int> emap;        // n * n: (row position, column position) -> entry or -1
+    std::vector<int> cstart;      // n + 1: first entry of each column
+    std::vector<uint64_t> cmask;  // 2 n: rows holding an entry in column j (bits 0-63, 64-127)
     std::vector<uint8_t> apat;    // n * n: structural pattern of the bordered matrix (before fill)
     // LU, level by level: scale the L entries of the level's pivots
     // (b items: e_ik | e_kk << 16), then the Schur updates (c items:

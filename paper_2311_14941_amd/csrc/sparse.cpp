@@ -145,14 +145,23 @@ void compile_sparse(Mech &m)
         for (int i : Lc[k])
             for (int j : Ur[k]) F[i * n + j] = 1;
     }
+    // entries numbered column by column, rows ascending within a column, so
+    // a column's entries are contiguous: the entry of (i, j) is the column's
+    // start plus the number of its rows above i (what the device solves
+    // compute from the column's row mask)
     S.emap.assign((size_t)n * n, -1);
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j)
+    S.cstart.assign(1, 0);
+    S.cmask.assign(2 * (size_t)n, 0);
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < n; ++i)
             if (F[i * n + j]) {
                 S.emap[i * n + j] = (int)S.erow.size();
                 S.erow.push_back(i);
                 S.ecol.push_back(j);
+                S.cmask[2 * j + i / 64] |= 1ull << (i % 64);
             }
+        S.cstart.push_back((int)S.erow.size());
+    }
     S.nnz = (int)S.erow.size();
     if (S.nnz >= NOENT) throw Unsupported("sparse LU has too many entries for 16-bit entry indices");
     auto E = [&](int i, int j) { return S.emap[i * n + j]; };

@@ -43,12 +43,13 @@ __device__ __forceinline__ double vsum(const double (&a)[VPL])
     return wave_sum(s);
 }
 
-// the temperature component (c = N) sits in slot VPL - 1 (VPL is the least
-// number of slots that holds N + 1 components)
+// the temperature component c = N sits in slot N / 64, lane N % 64 (with
+// two slots per lane, N = 63 still has it in the first)
 template <int VPL>
 __device__ __forceinline__ double comp_T(const DevMech &m, const double (&y)[VPL])
 {
-    return rdlane(y[VPL - 1], m.N - 64 * (VPL - 1));
+    if (VPL == 1 || m.N < 64) return rdlane(y[0], m.N & 63);
+    return rdlane(y[VPL - 1], m.N & 63);
 }
 
 template <int VPL>
@@ -403,13 +404,70 @@ __device__ __forceinline__ void sweep(const double *E, double *X, const int *lvl
 // The vector is moved to position order and swept in registers, one column
 // of L (then of the unit-diagonal U) per iteration: the pivot value is
 // broadcast with readlane and every lane whose row holds an entry in that
-// column updates its component; entries come from the column-major entry
-// map.  No barrier inside the sweeps (one wave).
+// column updates its component.  Entries are numbered column by column, so
+// a lane's entry in column k is the column's start plus the number of
+// entries in the rows above it: a count of the column's row mask below the
+// lane (mbcnt), with the mask and start read as wave-uniform values.  No
+// barrier and no per-lane index load inside the sweeps.
 template <int VPL>
 __device__ __forceinline__ double rd_pos(const double (&z)[VPL], int k)
 {
     if (VPL == 1 || k < 64) return rdlane(z[0], k);
     return rdlane(z[VPL - 1], k - 64);
+}
+
+// lanes below this one that are set in m
+__device__ __forceinline__ int below(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return (uint64_t)hi << 32 | lo;
+}
+
+// The columns' row masks and entry starts, held one column per lane
+// (column lane + 64 w in slot w), loaded once per solve.
+template <int VPL>
+struct ColMeta {
+    uint64_t m0[VPL], m1[VPL];
+    int start[VPL];
+};
+
+template <int VPL>
+__device__ __forceinline__ ColMeta<VPL> col_meta(const DevSparse &sp, int lane)
+{
+    ColMeta<VPL> c;
+#pragma unroll
+    for (int w = 0; w < VPL; ++w) {
+        const int k = lane + 64 * w;
+        const bool ok = k < sp.n;
+        c.m0[w] = ok ? sp.cmask[2 * k] : 0;
+        c.m1[w] = ok && VPL > 1 ? sp.cmask[2 * k + 1] : 0;
+        c.start[w] = ok ? sp.cstart[k] : 0;
+    }
+    return c;
+}
+
+// This lane's factor value in column k for each slot (0 where its row has
+// no entry there).  An absent entry's index still lies inside the LDS
+// allocation (at most the column's end), and the select keeps whatever it
+// holds out of the result.
+template <int VPL>
+__device__ __forceinline__ void col_values(const ColMeta<VPL> &c, const double *E, int k, int lane,
+                                           double (&val)[VPL])
+{
+    const int w = VPL == 1 ? 0 : k >> 6, kk = k & 63;
+    const uint64_t m0 = rdlane64(c.m0[w], kk);
+    const int base = __builtin_amdgcn_readlane(c.start[w], kk);
+    val[0] = (m0 >> lane) & 1 ? E[base + below(m0)] : 0.0;
+    if (VPL > 1) {
+        const uint64_t m1 = rdlane64(c.m1[w], kk);
+        val[VPL - 1] = (m1 >> lane) & 1 ? E[base + __builtin_popcountll(m0) + below(m1)] : 0.0;
+    }
 }
 
 template <int VPL>
@@ -420,6 +478,7 @@ __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, cons
     const double *E = lds + sp.E;
     double *X = lds + sp.X;
     const double *DINV = lds + sp.DINV;
+    const ColMeta<VPL> cm = col_meta<VPL>(sp, lane);
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
         const int c = lane + 64 * v;
@@ -434,50 +493,35 @@ __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, cons
         const int q = lane + 64 * v;
         z[v] = q < n ? X[q] : 0.0;
     }
-    // forward: x_i -= l_ik x_k, k ascending (the next column's entry
-    // indices are loaded one iteration ahead)
-    uint16_t enx[VPL];
-#pragma unroll
-    for (int v = 0; v < VPL; ++v) {
-        const int q = lane + 64 * v;
-        enx[v] = q < n ? sp.colmap[q] : sc::NOENT;
-    }
+    // forward: x_i -= l_ik x_k, k ascending, rows below the diagonal (the
+    // next column's values are read while this one is applied)
+    double nxt[VPL], cur[VPL];
+    col_values<VPL>(cm, E, 0, lane, nxt);
     for (int k = 0; k < n - 1; ++k) {
-        uint16_t e[VPL];
 #pragma unroll
-        for (int v = 0; v < VPL; ++v) {
-            const int q = lane + 64 * v;
-            e[v] = q > k ? enx[v] : sc::NOENT;
-            enx[v] = q < n ? sp.colmap[(k + 1) * n + q] : sc::NOENT;
-        }
+        for (int v = 0; v < VPL; ++v) cur[v] = nxt[v];
+        if (k + 1 < n - 1) col_values<VPL>(cm, E, k + 1, lane, nxt);
         const double zk = rd_pos<VPL>(z, k);
 #pragma unroll
         for (int v = 0; v < VPL; ++v)
-            if (e[v] != sc::NOENT) z[v] = fma(-E[e[v]], zk, z[v]);
+            if (lane + 64 * v > k) z[v] = fma(-cur[v], zk, z[v]);
     }
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
         const int q = lane + 64 * v;
         if (q < n) z[v] *= DINV[q];
     }
-    // backward with the unit-diagonal U: x_i -= u'_ik x_k, k descending
-#pragma unroll
-    for (int v = 0; v < VPL; ++v) {
-        const int q = lane + 64 * v;
-        enx[v] = q < n ? sp.colmap[(n - 1) * n + q] : sc::NOENT;
-    }
+    // backward with the unit-diagonal U: x_i -= u'_ik x_k, k descending,
+    // rows above the diagonal
+    col_values<VPL>(cm, E, n - 1, lane, nxt);
     for (int k = n - 1; k > 0; --k) {
-        uint16_t e[VPL];
 #pragma unroll
-        for (int v = 0; v < VPL; ++v) {
-            const int q = lane + 64 * v;
-            e[v] = q < k ? enx[v] : sc::NOENT;
-            enx[v] = q < n ? sp.colmap[(k - 1) * n + q] : sc::NOENT;
-        }
+        for (int v = 0; v < VPL; ++v) cur[v] = nxt[v];
+        if (k > 1) col_values<VPL>(cm, E, k - 1, lane, nxt);
         const double zk = rd_pos<VPL>(z, k);
 #pragma unroll
         for (int v = 0; v < VPL; ++v)
-            if (e[v] != sc::NOENT) z[v] = fma(-E[e[v]], zk, z[v]);
+            if (lane + 64 * v < k) z[v] = fma(-cur[v], zk, z[v]);
     }
     __syncthreads();  // every lane has read X
 #pragma unroll
@@ -600,8 +644,10 @@ template <int VPL>
 __device__ void integrate_cell_v(const DevMech &m, const DevSparse &sp, const Opts &o, double *lds, int64_t c,
                                  int lane, const double *T0, const double *P, const double *Y0, int64_t ld,
                                  const double *DT, const double *dlnA, double *h_io, double *T1, double *Y1,
-                                 int32_t *status, int32_t *nacc_out, int32_t *nrej_out)
+                                 int32_t *status, int32_t *nacc_out, int32_t *nrej_out, const int32_t *ref)
 {
+    // a cell mapped onto another cell's result is left to the mapping pass
+    if (ref && ref[c] != c) return;
     double y[VPL];
     load_state_v<VPL>(m, T0, Y0, ld, c, lane, y);
     const double p = P[c], dt = DT[c];
@@ -624,22 +670,25 @@ __device__ void integrate_cell_v(const DevMech &m, const DevSparse &sp, const Op
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-// (capping the registers for two waves per SIMD, which the LDS of a
-// 53-species cell would allow, spills 78-117 registers to scratch: one wave
-// per SIMD it is)
-#define SP_OCC
+// One-wave mechanisms (VPL = 1) run two waves per SIMD: their LDS allows it
+// (under 20 KB per cell up to 53 species) and the second wave hides the
+// first's LDS, memory and broadcast latencies.  The register cap this
+// implies spills about a hundred registers to scratch, outside the inner
+// loops; measured on the 53-species batch it is still 1.6x faster than one
+// wave per SIMD.
+#define SP_OCC __attribute__((amdgpu_waves_per_eu(VPL == 1 ? 2 : 1, VPL == 1 ? 2 : 1)))
 template <int VPL, bool CV>
 __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp(DevMech mk, DevSparse sp, Opts o, int64_t n,
                                                        const double *T0, const double *P, const double *Y0,
                                                        int64_t ld, const double *DT, const double *dlnA,
                                                        double *h_io, double *T1, double *Y1, int32_t *status,
-                                                       int32_t *nacc, int32_t *nrej)
+                                                       int32_t *nacc, int32_t *nrej, const int32_t *ref)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
     const int64_t c = blockIdx.x;
     if (c >= n) return;
-    integrate_cell_v<VPL>(m, sp, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej);
+    integrate_cell_v<VPL>(m, sp, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej, ref);
 }
 
 template <int VPL, bool CV>
@@ -649,7 +698,7 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_persistent(DevMech
                                                                   const double *dlnA, double *h_io, double *T1,
                                                                   double *Y1, int32_t *status, int32_t *nacc,
                                                                   int32_t *nrej, unsigned long long *queue,
-                                                                  const int32_t *perm, int tile)
+                                                                  const int32_t *perm, int tile, const int32_t *ref)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
@@ -665,7 +714,7 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_persistent(DevMech
         for (int64_t i = (int64_t)base; i < end; ++i) {
             const int64_t c = perm ? (int64_t)perm[i] : i;
             integrate_cell_v<VPL>(m, sp, o, lds, c, lane, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc,
-                                  nrej);
+                                  nrej, ref);
         }
     }
 }
@@ -676,7 +725,7 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_static(DevMech mk,
                                                               int64_t ld, const double *DT, const double *dlnA,
                                                               double *h_io, double *T1, double *Y1,
                                                               int32_t *status, int32_t *nacc, int32_t *nrej,
-                                                              int64_t group)
+                                                              int64_t group, const int32_t *ref)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
@@ -685,7 +734,7 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_static(DevMech mk,
 #pragma unroll 1
     for (int64_t c = c0; c < c1; ++c)
         integrate_cell_v<VPL>(m, sp, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc,
-                              nrej);
+                              nrej, ref);
 }
 
 template <int VPL, bool CV>
@@ -819,10 +868,10 @@ hipError_t launch_linsolve_sp(int vpl, const DevMech &m, const DevSparse &sp, in
 hipError_t launch_integrate_sp(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o, int64_t n,
                                const double *T0, const double *p, const double *Y0, int64_t ld, const double *dt,
                                const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na,
-                               int32_t *nr, hipStream_t s)
+                               int32_t *nr, const int32_t *ref, hipStream_t s)
 {
     SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp), dim3((unsigned)n), dim3(WAVE), sp_lds(sp),
-                                               s, m, sp, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr));
+                                               s, m, sp, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, ref));
     return hipGetLastError();
 }
 
@@ -831,24 +880,25 @@ hipError_t launch_integrate_sp_persistent(int vpl, const DevMech &m, const DevSp
                                           int64_t ld, const double *dt, const double *dlnA, double *h_io,
                                           double *T1, double *Y1, int32_t *st, int32_t *na, int32_t *nr,
                                           unsigned long long *queue, const int32_t *perm, int tile, int grid,
-                                          hipStream_t s)
+                                          const int32_t *ref, hipStream_t s)
 {
     SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp_persistent), dim3((unsigned)grid),
                                                dim3(WAVE), sp_lds(sp), s, m, sp, o, n, T0, p, Y0, ld, dt, dlnA,
-                                               h_io, T1, Y1, st, na, nr, queue, perm, tile));
+                                               h_io, T1, Y1, st, na, nr, queue, perm, tile, ref));
     return hipGetLastError();
 }
 
 hipError_t launch_integrate_sp_static(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o, int64_t n,
                                       const double *T0, const double *p, const double *Y0, int64_t ld,
                                       const double *dt, const double *dlnA, double *h_io, double *T1, double *Y1,
-                                      int32_t *st, int32_t *na, int32_t *nr, int grid, hipStream_t s)
+                                      int32_t *st, int32_t *na, int32_t *nr, int grid, const int32_t *ref,
+                                      hipStream_t s)
 {
     const int64_t group = (n + grid - 1) / grid;
     const unsigned g = (unsigned)((n + group - 1) / group);
     SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp_static), dim3(g), dim3(WAVE), sp_lds(sp), s,
                                                m, sp, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr,
-                                               group));
+                                               group, ref));
     return hipGetLastError();
 }
 

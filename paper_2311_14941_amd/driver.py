@@ -1,4 +1,5 @@
-"""Operator-split driver with local time stepping (paper Sec. 2.5).
+"""Operator-split driver with local time stepping (paper Sec. 2.5), with
+optional zonal reference-cell mapping of the chemistry.
 
 Each split step integrates the chemistry of every cell of a 2-D grid over
 that cell's own time step (a CFL-limited local step, so the batch is
@@ -29,9 +30,12 @@ class SplitDriver:
                   for the transport update to stay bounded
     dx, diffusivity  grid spacing [m] and diffusion coefficient [m^2/s]
     inflow_T, inflow_Y  inflow profile at x = 0: [ny] and [N, ny]
+    mapping       None, or a dict (Y_fuel, Y_ox, z_tol, dT, dlnp) for zonal
+                  reference-cell mapping of the chemistry (Plan.set_mapping):
+                  low-reactivity cells take their zone reference's change
     """
 
-    def __init__(self, plan: Plan, nx, ny, p, u, dt, dx, diffusivity, inflow_T, inflow_Y):
+    def __init__(self, plan: Plan, nx, ny, p, u, dt, dx, diffusivity, inflow_T, inflow_Y, mapping=None):
         t = plan.torch
         self.plan, self.nx, self.ny = plan, int(nx), int(ny)
         n = self.nx * self.ny
@@ -59,6 +63,11 @@ class SplitDriver:
         self.status, self.n_acc, self.n_rej = mk(), mk(), mk()
         self.steps = t.zeros(n, dtype=t.int64, device=dev)
         self.failed = t.zeros(n, dtype=t.int64, device=dev)
+        self.ref = None
+        if mapping is not None:
+            plan.set_mapping(mapping["Y_fuel"], mapping["Y_ox"], mapping["z_tol"], mapping["dT"],
+                             mapping.get("dlnp", 0.0))
+            self.ref = t.empty(n, dtype=t.int32, device=dev)
 
     def load(self, T, Y, h=None):
         """Set the state: T [cells], Y [N, cells]; step sizes restart unless h is given."""
@@ -72,9 +81,12 @@ class SplitDriver:
         """Integrate every cell over its dt: q[0] -> q[1]."""
         a, b, N, n = self.q[0], self.q[1], self.N, self.n
         plan = self.plan
-        _check(lib().sc_integrate(plan._h, n, _ptr(a[N]), _ptr(self.p), _ptr(a[:N]), n, _ptr(self.dt), None,
-                                  _ptr(self.h), _ptr(b[N]), _ptr(b[:N]), _ptr(self.status), _ptr(self.n_acc),
-                                  _ptr(self.n_rej), _stream(plan.torch, plan.device)))
+        args = (plan._h, n, _ptr(a[N]), _ptr(self.p), _ptr(a[:N]), n, _ptr(self.dt), None, _ptr(self.h),
+                _ptr(b[N]), _ptr(b[:N]), _ptr(self.status), _ptr(self.n_acc), _ptr(self.n_rej))
+        if self.ref is None:
+            _check(lib().sc_integrate(*args, _stream(plan.torch, plan.device)))
+        else:
+            _check(lib().sc_integrate_mapped(*args, _ptr(self.ref), _stream(plan.torch, plan.device)))
         self.steps.add_(self.n_acc).add_(self.n_rej)
         self.failed.add_((self.status != 0).long())
 

@@ -66,4 +66,42 @@ def flame_field(nx=170, ny=170, dx=1.0e-3, D=2.0e-4, cfl=0.5, seed=301):
     Y = np.repeat(Yin, nx, axis=0)                     # [ny*nx, N]
     return dict(mech=mech, nx=nx, ny=ny, dx=dx, D=D, T=T, p=np.full(nx * ny, P_ATM), Y=Y,
                 u=u.reshape(-1), dt=dt.reshape(-1), inflow_T=Tin, inflow_Y=Yin.T.copy(),
-                stream=np.repeat(stream, nx), N=N)
+                stream=np.repeat(stream, nx), N=N, Y_fuel=jet, Y_ox=air)
+
+
+def mixing_cells(n=512, seed=302):
+    """Cells of the flame's mixing layers, for the reference-cell mapping:
+    the jet and air streams of flame_field (the mapping's fuel and
+    oxidiser), and per cell one of
+      * coflow air at 291 K plus 0-2 K (40%),
+      * air with a trace of jet or pilot gas, mass fraction 10^U[-6,-2.7],
+        at 291-300 K (25%),
+      * a jet/air mixture of jet fraction U[0,1] at the mixing temperature of
+        the two streams (20%),
+      * pilot gas (the 1880 K burnt lean mixture of flame_field) mixed with
+        up to 30% air, at 1500-1880 K (15%);
+    1 atm, local dt log-uniform over the flame field's range (1e-5 to
+    5.6e-4 s).  Rows of Y are [n, N]."""
+    f = flame_field(nx=2, ny=170)
+    mech = f["mech"]
+    jet, air = f["Y_fuel"], f["Y_ox"]
+    pilot = f["inflow_Y"][:, f["inflow_T"] > 1000.0][:, 0]
+    rng = np.random.default_rng(seed)
+    kind = rng.choice(4, size=n, p=[0.40, 0.25, 0.20, 0.15])
+    Y = np.empty((n, mech.n_species))
+    T = np.empty(n)
+    for c in range(n):
+        if kind[c] == 0:
+            Y[c], T[c] = air, 291.0 + 2.0 * rng.uniform()
+        elif kind[c] == 1:
+            a = 10.0 ** rng.uniform(-6.0, -2.7)
+            src = jet if rng.uniform() < 0.5 else pilot
+            Y[c], T[c] = a * src + (1 - a) * air, 291.0 + 9.0 * rng.uniform()
+        elif kind[c] == 2:
+            a = rng.uniform()
+            Y[c], T[c] = a * jet + (1 - a) * air, 294.0 * a + 291.0 * (1 - a)
+        else:
+            a = rng.uniform(0.0, 0.3)
+            Y[c], T[c] = a * air + (1 - a) * pilot, rng.uniform(1500.0, 1880.0)
+    dt = 10.0 ** rng.uniform(-5.0, np.log10(5.6e-4), n)
+    return dict(mech=mech, T=T, p=np.full(n, P_ATM), Y=Y, dt=dt, kind=kind, Y_fuel=jet, Y_ox=air)

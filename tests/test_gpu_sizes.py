@@ -16,6 +16,10 @@ pytestmark = pytest.mark.gpu
 # (species, reactions, pool fraction, seed): seeded synthetic C/H/O/N mechanisms
 SIZES = {15: (15, 60, 0.15, 400), 24: (24, 120, 0.5, 400), 31: (31, 160, 0.5, 400),
          55: (55, 330, 0.15, 400), 63: (63, 400, 0.15, 400)}
+# the sparse kernels hold the N + 2 positions of the bordered system in one
+# slot per lane up to 64 positions (N = 62 fills them), two beyond (N = 63
+# is the smallest two-slot case); N = 14 fills 16 positions
+SPARSE_SIZES = {14: (14, 56, 0.15, 401), 62: (62, 390, 0.15, 401)}
 
 
 @pytest.fixture(scope="module")
@@ -39,7 +43,7 @@ def case(n_species, ncell=12):
     from oracle.oracle import Oracle
     from synth.mechgen import make_mechanism
     if n_species not in _MECH:
-        n, r, pf, seed = SIZES[n_species]
+        n, r, pf, seed = SIZES.get(n_species) or SPARSE_SIZES[n_species]
         mech = make_mechanism(n, r, r // 10, r // 20, ["C", "H", "O", "N"], seed=seed, pool_frac=pf)
         _MECH[n_species] = (mech, Oracle(mech.to_text()))
     mech, o = _MECH[n_species]
@@ -178,3 +182,55 @@ def test_size_adjoint_fixed_steps(torch, sc, ns, T0, dt):
         err = np.max(np.abs(got - ref) / den)
         print(f"N={ns} cell {c}: adjoint vs central differences {err:.3g}")
         assert err < 1e-4, (ns, c, err)
+
+
+@pytest.mark.parametrize("ns", [14, 15, 62, 63])
+def test_size_sparse_parity(torch, sc, ns):
+    """The sparse linear algebra at the edges of its one- and two-slot
+    layouts: Jacobian (recovered from the bordered matrix) against the
+    complex-step derivative, one linear solve against a dense solve of the
+    complex-step matrix (normwise residual; the solution where the matrix is
+    well conditioned), integration at rtol 1e-10 against the oracle at rtol
+    1e-11 (the parity bar), and queue and plain launches bit for bit."""
+    mech, o, T, p, Y = case(ns)
+    m = sc.Mechanism(mech.to_text())
+    plan = sc.Plan(m, linalg="sparse")
+    Tg, pg, Yg = _gpu(torch, T, p, Y)
+    J = plan.jacobian(Tg, pg, Yg).cpu().numpy()
+    n1 = mech.n_species + 1
+    rng = np.random.default_rng(ns)
+    hg = np.full(T.size, 1e-7)
+    b = rng.normal(size=(T.size, n1))
+    x = plan.linsolve(Tg, pg, Yg, torch.tensor(hg, device="cuda:0"),
+                      torch.tensor(b, device="cuda:0")).cpu().numpy()
+    for c in range(T.size):
+        y = np.append(Y[c], T[c])
+        Jc = o.jac_cs(y, p[c])
+        row = np.abs(Jc).max(1, keepdims=True) + 1e-300
+        assert (np.abs(J[c] - Jc) / (1e-8 * np.abs(Jc) + 1e-12 * row)).max() <= 1.0, (ns, c)
+        M = np.eye(n1) / hg[c] - Jc
+        ref = np.linalg.solve(M, b[c])
+        res = np.abs(M @ x[c] - b[c]).max() / (np.abs(M).max() * np.abs(x[c]).max() + np.abs(b[c]).max())
+        assert res < 1e-12, (ns, c, res)
+        # the solution itself only where the matrix's conditioning bounds its
+        # error (these random states give condition numbers up to 1e18, where
+        # any two backward-stable solves may differ completely)
+        if np.linalg.cond(M) < 1e8:
+            assert np.allclose(x[c], ref, rtol=1e-7, atol=1e-9 * np.abs(ref).max()), (ns, c)
+    dt = np.full(T.size, 1e-6)
+    ref = o.integrate(T, p, Y, dt, rtol=1e-11, atol=1e-17, max_steps=200000)
+    assert np.all(ref["status"] == 0)
+    Tg, pg, Yg, dtg = _gpu(torch, T, p, Y, dt)
+    r = sc.Plan(m, rtol=1e-10, atol=1e-16, max_steps=200000, linalg="sparse").integrate(Tg, pg, Yg, dtg)
+    assert np.all(r["status"].cpu().numpy() == 0)
+    T1, Y1 = r["T"].cpu().numpy(), r["Y"].cpu().numpy().T
+    assert np.all(np.abs(T1 - ref["T"]) <= 1e-6 * ref["T"]), ns
+    big = np.abs(ref["Y"]) > 1e-8
+    assert np.all(np.abs(Y1 - ref["Y"])[big] <= 1e-6 * np.abs(ref["Y"])[big]), ns
+    assert np.all(np.abs(Y1 - ref["Y"])[~big] <= 1e-12), ns
+    a = sc.Plan(m, linalg="sparse").integrate(Tg, pg, Yg, dtg)
+    q = sc.Plan(m, mode="persistent", order="cost", linalg="sparse")
+    bq = q.integrate(Tg, pg, Yg, dtg)
+    bq = q.integrate(Tg, pg, Yg, dtg, out=bq)
+    for k in ("T", "Y", "status", "n_acc", "n_rej"):
+        assert torch.equal(a[k], bq[k]), (ns, k)
