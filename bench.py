@@ -82,14 +82,20 @@ def main():
     ap.add_argument("--order", default="none", choices=["none", "dt", "cost"],
                     help="persistent mode: cell order (cost: the previous call's step counts)")
     ap.add_argument("--tile", type=int, default=1)
-    ap.add_argument("--linalg", default="auto", choices=["auto", "dense", "sparse"],
-                    help="linear algebra of the implicit stages (auto: dense up to 63 species)")
+    ap.add_argument("--linalg", default="sparse", choices=["auto", "dense", "sparse"],
+                    help="linear algebra of the implicit stages (default sparse, the faster family; auto: "
+                         "the library's choice, dense up to 63 species; the extrapolation baseline runs dense)")
+    ap.add_argument("--cells-per-wave", type=int, default=0,
+                    help="sparse linear algebra: cells per 64-lane wave (0: the most that fit)")
     ap.add_argument("--method", default="ros4", choices=["ros4", "extrap"],
                     help="c2/c2v: integration method (extrap: the extrapolation baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--spinup", type=int, default=400,
                     help="lts workload: untimed split steps before the warm-up and the timed steps")
     ap.add_argument("--no-gradient", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="c1/c2: time the tuned launch only (no launch variants, host-to-host or parity "
+                         "blocks; for profiler runs)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c2v", "c1", "c3", "c3s", "c5", "c5s", "lts", "copy"],
                     help="c2: the headline (default); c2v: the same cells as constant-volume reactors; "
                          "c1: the 9-species workload's 1,024 cells (tiled to --cells); "
@@ -118,6 +124,8 @@ def main():
         return bench_copy(args)
     if args.workload == "lts":
         return bench_lts(args)
+    if args.method == "extrap":
+        args.linalg = "dense"  # the baseline integrator exists in the dense family only
     c1 = args.workload == "c1"
     log("bench: generating the " + ("C1" if c1 else "C2") + " workload")
     cells = make_cells("C1" if c1 else "C2")
@@ -157,7 +165,9 @@ def main():
     else:
         launch = dict(mode=args.mode, tile=args.tile, grid=0, order=args.order)
         tune_ms = None
-    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, method=args.method, linalg=args.linalg, **launch)
+    cpw = launch.pop("cells_per_wave", args.cells_per_wave) if args.linalg == "sparse" else 0
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, method=args.method, linalg=args.linalg,
+                   cells_per_wave=cpw, **launch)
     use_pred = launch["mode"] == "persistent" and launch["order"] == "cost"
     stream = torch.cuda.current_stream()
     out = None
@@ -218,7 +228,8 @@ def main():
                    "failed_cells": failed,
                    "cost_order_counts": ("predicted: step counts of a perturbed copy of the batch (T0, p within "
                                          "+-1%), copied in before every timed call" if use_pred else None),
-                   "kernel": kernel_name(launch, args.linalg, mech.N), "linalg": args.linalg,
+                   "kernel": kernel_name(launch, args.linalg, mech.N, cpw), "linalg": args.linalg,
+                   "cells_per_wave": resolved_cpw(args.linalg, mech.N, cpw),
                    "steps_per_cell_mean": float((nacc + nrej).mean()),
                    # where the work is: share of attempted steps and mean per cell by class
                    # (unburnt / near ignition / equilibrated)
@@ -231,19 +242,25 @@ def main():
         "paper_context": "the paper reports no chemistry throughput; its combined CPU strategy is >= 31x the "
                          "standard solver on a whole ~29,000-cell CFD run (16 MPI subdomains + OpenMP, CPU)",
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None if constv or c1 else measured_traffic(launch),
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None if constv or c1 else measured_traffic(launch, kernel_name(launch, args.linalg,
+                                                                                                mech.N, cpw)),
                      "kernel_ms": kern_s * 1e3, "flops_per_launch": flops},
     }
     # the same batch through the other launches (results bitwise equal):
     # plain one-workgroup-per-cell, the queue in index order, and the queue
     # ordered by the batch's own exact counts (an upper bound: a real call
     # cannot know them)
+    if args.no_extras:
+        print(json.dumps(res), flush=True)
+        return
     variants = {}
     for name, cfg, counts in (("plain", dict(mode="plain"), None),
                               ("persistent_index_order", dict(mode="persistent", order="none"), None),
                               ("persistent_cost_exact_upper_bound", dict(mode="persistent", order="cost"),
                                (out["n_acc"].clone(), out["n_rej"].clone()))):
-        pp = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, method=args.method, linalg=args.linalg, **cfg)
+        pp = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, method=args.method, linalg=args.linalg,
+                     cells_per_wave=cpw, **cfg)
         o2 = pp.integrate(T, p, Y, dt)
         ms = []
         for _ in range(2):
@@ -392,7 +409,8 @@ def parity_block(sc, torch, mech, cells, idx, out, T, p, Y, dt, reactor, args):
     return res
 
 
-KERNEL_SOURCES = ("paper_2311_14941_amd/csrc/core.hpp", "paper_2311_14941_amd/csrc/kernels.hip")
+KERNEL_SOURCES = ("paper_2311_14941_amd/csrc/core.hpp", "paper_2311_14941_amd/csrc/kernels.hip",
+                  "paper_2311_14941_amd/csrc/sparse.hip", "paper_2311_14941_amd/csrc/devmech.hpp")
 
 
 def step_flops(info, method):
@@ -410,13 +428,23 @@ def step_flops(info, method):
     return 4 * (jac + info["flops_lu_sparse"]) + 6 * info["flops_rhs"] + 10 * info["flops_solve_sparse"]
 
 
-def kernel_name(launch, linalg, N):
-    """The integration kernel a launch runs (for the profile summaries)."""
+def resolved_cpw(linalg, N, requested=0):
+    """Cells per wave a plan runs: the sparse kernels fit 4 cells of up to
+    16 positions (N + 2), 2 of up to 32, else 1; the dense kernels 1."""
+    if linalg != "sparse" and not (linalg == "auto" and N + 1 > 64):
+        return 1
+    return requested or (4 if N + 2 <= 16 else 2 if N + 2 <= 32 else 1)
+
+
+def kernel_name(launch, linalg, N, cpw=0):
+    """The integration kernel a launch runs (for the profile summaries):
+    template arguments <slots per lane, cells per wave> for the sparse kernels."""
     mode = launch["mode"]
     if linalg == "sparse" or (linalg == "auto" and N + 1 > 64):
-        vpl = 1 if N + 1 <= 64 else 2
-        return {"plain": f"k_integrate_sp<{vpl}>", "persistent": f"k_integrate_sp_persistent<{vpl}>",
-                "static": f"k_integrate_sp_static<{vpl}>"}[mode]
+        vpl = 1 if N + 2 <= 64 else 2
+        g = resolved_cpw(linalg, N, cpw)
+        return {"plain": f"k_integrate_sp<{vpl},{g}>", "persistent": f"k_integrate_sp_persistent<{vpl},{g}>",
+                "static": f"k_integrate_sp_static<{vpl},{g}>"}[mode]
     npd = 16 if N + 1 <= 16 else 32 if N + 1 <= 32 else 56 if N + 1 <= 56 else 64
     return {"plain": f"k_integrate<{npd}>", "persistent": f"k_integrate_persistent<{npd}>",
             "static": f"k_integrate_static<{npd}>"}[mode]
@@ -431,19 +459,19 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launch):
+def measured_traffic(launch, kernel):
     """HBM bytes per launch of the integration kernel from the committed
     counter runs (profiles/k_integrate_c2_traffic.json: FETCH_SIZE and
     WRITE_SIZE of the kernel, each divided by the bytes-per-byte ratio the
     same counter reads for a plain copy of known size), or None when the
-    kernel sources changed since those runs or they cover another launch
-    configuration."""
+    kernel sources changed since those runs or they cover another kernel or
+    launch configuration."""
     path = os.path.join(ROOT, "profiles", "k_integrate_c2_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_digest") != kernel_digest() or t.get("launch") != launch:
+    if t.get("kernel_digest") != kernel_digest() or t.get("launch") != launch or t.get("kernel") != kernel:
         return None
     return t["traffic_bytes"]
 
@@ -501,6 +529,19 @@ def bench_chained(args):
     Tf, Yf, _, steps = chain.run(T, Y)
     torch.cuda.synchronize()
     fwd_ms = (time.perf_counter() - t0) * 1e3
+    if mech.N + 1 > 64:
+        # the adjoint is the dense family's (N <= 63): forward only here
+        line = {"metric": "chained substeps: forward wall time", "unit": "ms", "value": fwd_ms,
+                "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                "config": {"workload": f"{key}: 65,536 cells, {mech.N}-species mechanism, C2 classes, 20 chained "
+                                       "substeps of 5e-5 s (state and step size carried), rtol 1e-6",
+                           "substeps": nsub, "linalg": args.linalg,
+                           "gradient": "not run: the adjoint supports up to 63 species (dense family)"},
+                "forward_graph_ms": fwd_ms, "cells_per_s": T.numel() * nsub / (fwd_ms / 1e3),
+                "steps_per_cell_mean": float(steps.double().mean().item()),
+                "failed_cells_last_substep": int((chain.status != 0).sum().item())}
+        print(json.dumps(line), flush=True)
+        return
     log("bench: gradient through autograd")
     torch.cuda.reset_peak_memory_stats()
     free0, total = torch.cuda.mem_get_info()

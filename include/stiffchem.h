@@ -128,6 +128,13 @@ typedef struct {
     int32_t reactor;    /* SC_REACTOR_CONST_P (default) or SC_REACTOR_CONST_V */
     int32_t method;     /* SC_METHOD_ROS4 (default) or SC_METHOD_EXTRAP */
     int32_t linalg;     /* SC_LINALG_AUTO (default), SC_LINALG_DENSE or SC_LINALG_SPARSE */
+    int32_t cells_per_wave; /* sparse linear algebra: cells integrated side by side in
+                           one 64-lane wave, 1, 2 or 4 (each cell then takes 64, 32 or 16
+                           lanes, so N + 2 must fit them); 0 (default) = the most that
+                           fit.  Other values, or more than 1 with the dense linear
+                           algebra: SC_EINVAL.  Results agree with one cell per wave to
+                           rounding (a cell's reductions and rate sums run over fewer
+                           lanes in another order), not bit for bit. */
 } sc_options;
 
 typedef struct {

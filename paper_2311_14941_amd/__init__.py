@@ -39,7 +39,8 @@ class Options(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32),
                 ("mode", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32),
                 ("order", C.c_int32), ("fixed_step", C.c_int32), ("hmax_frac", C.c_double),
-                ("reactor", C.c_int32), ("method", C.c_int32), ("linalg", C.c_int32)]
+                ("reactor", C.c_int32), ("method", C.c_int32), ("linalg", C.c_int32),
+                ("cells_per_wave", C.c_int32)]
 
 
 class Mapping(C.Structure):
@@ -175,11 +176,13 @@ class Plan:
     reactor: "const_p" (the per-cell p arguments are pressures) or "const_v"
     (a rigid vessel: they are densities in kg/m^3; forward calls only).
     method: "ros4" (the Rosenbrock method) or "extrap" (the linearly implicit
-    Euler extrapolation baseline; forward only)."""
+    Euler extrapolation baseline; forward only).
+    linalg: "auto", "dense" or "sparse"; cells_per_wave (sparse): 1, 2 or 4
+    cells side by side in one wave, 0 for the most that fit."""
 
     def __init__(self, mech: Mechanism, device: int = 0, rtol=1e-6, atol=1e-12, max_steps=100000,
                  mode="plain", tile=1, grid=0, order="none", fixed_step=False, hmax_frac=0.0,
-                 reactor="const_p", method="ros4", linalg="auto"):
+                 reactor="const_p", method="ros4", linalg="auto", cells_per_wave=0):
         import torch
         self.torch = torch
         self.mech = mech
@@ -193,6 +196,7 @@ class Plan:
         opt.reactor = REACTORS[reactor]
         opt.method = METHODS[method]
         opt.linalg = LINALGS[linalg]
+        opt.cells_per_wave = int(cells_per_wave)
         self.reactor, self.method, self.linalg = reactor, method, linalg
         self.config = dict(mode=mode, tile=tile, grid=grid, order=order)
         self.options = opt

@@ -285,9 +285,18 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
     // the sparse kernels' vectors hold every position of the bordered
     // system (N + 2 of them) in one or two slots per lane
     const int vpl = S.n <= 64 ? 1 : 2;
+    // cells per wave: each cell's group of 64 / cpw lanes must hold the N + 2 positions
+    const int cpw_max = !sparse ? 1 : S.n <= 16 ? 4 : S.n <= 32 ? 2 : 1;
+    if (o.cells_per_wave != 0 && o.cells_per_wave != 1 && o.cells_per_wave != 2 && o.cells_per_wave != 4)
+        return fail(SC_EINVAL, "cells_per_wave must be 0, 1, 2 or 4");
+    if (o.cells_per_wave > cpw_max)
+        return fail(SC_EINVAL, "cells_per_wave " + std::to_string(o.cells_per_wave) + " needs the sparse linear "
+                               "algebra and N + 2 <= " + std::to_string(64 / o.cells_per_wave) + " positions");
+    const int cpw = o.cells_per_wave ? o.cells_per_wave : cpw_max;
     scdev::DevSparse ds{};
     if (sparse) {
-        const int NV = 64 * vpl;
+        const int NV = 64 / cpw * vpl;
+        ds.cpw = cpw;
         ds.n = S.n;
         ds.nnz = S.nnz;
         ds.nl_lu = (int)S.lu_b_lvl.size() - 1;
@@ -307,7 +316,7 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
         ds.size = ds.DINV + S.n;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(SC_EHIP, "hipGetDeviceProperties failed");
-        if (sizeof(double) * (size_t)ds.size > prop.sharedMemPerBlock)
+        if (sizeof(double) * (size_t)ds.size * cpw > prop.sharedMemPerBlock)
             return fail(SC_EUNSUPPORTED, "the sparse factors of this mechanism need " +
                                              std::to_string(sizeof(double) * ds.size) +
                                              " bytes of LDS per cell; the device has " +
@@ -526,7 +535,8 @@ static sc_status integrate_impl(sc_plan *plan, int64_t n, const double *T0, cons
     }
     if (plan->opt.mode == SC_MODE_PERSISTENT) {
         const int tile = plan->opt.tile;
-        int64_t tiles = (n + tile - 1) / tile;
+        const int64_t per_pull = (int64_t)tile * (plan->sparse ? plan->ds.cpw : 1);  // cells one wave takes per pull
+        int64_t tiles = (n + per_pull - 1) / per_pull;
         int grid = plan->opt.grid > 0 ? plan->opt.grid : plan->capacity;
         if (grid <= 0) grid = 1;
         if (grid > tiles) grid = (int)tiles;

@@ -32,44 +32,86 @@ namespace scdev {
 
 
 // ---------------------------------------------------------------------------
+// lane geometry: G lanes per cell.  G = 64: one cell per wave, VPL slots per
+// lane.  G = 32 or 16: two or four cells per wave (mechanisms whose N + 2
+// positions fit G), each cell in its own aligned group of lanes with one
+// slot per lane.  Below, `lane` is the lane within the cell's group; sums
+// and broadcasts stay inside the group.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ double gsum(double v)
+{
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ double gbcast(double v, int k)
+{
+    if constexpr (G == WAVE)
+        return rdlane(v, k);
+    else
+        return __shfl(v, k, G);
+}
+
+template <int G>
+__device__ __forceinline__ int gbcast_i(int v, int k)
+{
+    if constexpr (G == WAVE)
+        return __builtin_amdgcn_readlane(v, k);
+    else
+        return __shfl(v, k, G);
+}
+
+template <int G>
+__device__ __forceinline__ bool gany(bool b)
+{
+    if constexpr (G == WAVE)
+        return __any(b);
+    else
+        return gsum<G>(b ? 1.0 : 0.0) > 0.0;
+}
+
+// ---------------------------------------------------------------------------
 // helpers over VPL components per lane
 // ---------------------------------------------------------------------------
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ __forceinline__ double vsum(const double (&a)[VPL])
 {
     double s = a[0];
 #pragma unroll
     for (int v = 1; v < VPL; ++v) s += a[v];
-    return wave_sum(s);
+    return gsum<G>(s);
 }
 
 // the temperature component c = N sits in slot N / 64, lane N % 64 (with
 // two slots per lane, N = 63 still has it in the first)
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ __forceinline__ double comp_T(const DevMech &m, const double (&y)[VPL])
 {
-    if (VPL == 1 || m.N < 64) return rdlane(y[0], m.N & 63);
-    return rdlane(y[VPL - 1], m.N & 63);
+    if (VPL == 1 || m.N < 64) return gbcast<G>(y[0], m.N & 63);
+    return gbcast<G>(y[VPL - 1], m.N & 63);
 }
 
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ __forceinline__ void load_state_v(const DevMech &m, const double *T, const double *Y, int64_t ld,
                                              int64_t cell, int lane, double (&y)[VPL])
 {
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int c = lane + 64 * v;
+        const int c = lane + G * v;
         y[v] = c < m.N ? Y[(int64_t)c * ld + cell] : c == m.N ? T[cell] : 0.0;
     }
 }
 
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ __forceinline__ void store_state_v(const DevMech &m, double *T, double *Y, int64_t ld, int64_t cell,
                                               int lane, const double (&y)[VPL])
 {
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int c = lane + 64 * v;
+        const int c = lane + G * v;
         if (c < m.N) Y[(int64_t)c * ld + cell] = y[v];
         if (c == m.N) T[cell] = y[v];
     }
@@ -79,20 +121,20 @@ __device__ __forceinline__ void store_state_v(const DevMech &m, double *T, doubl
 // thermodynamics, right-hand side and Jacobian terms
 // ---------------------------------------------------------------------------
 // Mixture state from y; writes C, g/RT, h/RT and clears the accumulators.
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ __forceinline__ Mix<> mixture_v(const DevMech &m, const DevSparse &sp, double *lds,
                                            const double (&y)[VPL], double p, Thermo<> (&th)[VPL], int lane)
 {
     const int N = m.N;
     Mix<> x;
-    x.T = comp_T<VPL>(m, y);
+    x.T = comp_T<VPL, G>(m, y);
     x.invT = 1.0 / x.T;
     x.lnT = log(x.T);
     x.p = p;
     double yw[VPL], cpw[VPL];
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int c = lane + 64 * v;
+        const int c = lane + G * v;
         th[v] = Thermo<>{0.0, 0.0, 0.0, 0.0};
         yw[v] = cpw[v] = 0.0;
         if (c < N) {
@@ -101,8 +143,8 @@ __device__ __forceinline__ Mix<> mixture_v(const DevMech &m, const DevSparse &sp
             cpw[v] = th[v].cpR * yw[v];
         }
     }
-    x.Wbar = 1.0 / vsum<VPL>(yw);
-    x.cp = m.Rgas * vsum<VPL>(cpw);
+    x.Wbar = 1.0 / vsum<VPL, G>(yw);
+    x.cp = m.Rgas * vsum<VPL, G>(cpw);
     if (m.cv) {
         x.rho = p;
         x.p = p * m.Rgas * x.T / x.Wbar;
@@ -112,7 +154,7 @@ __device__ __forceinline__ Mix<> mixture_v(const DevMech &m, const DevSparse &sp
     }
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int c = lane + 64 * v;
+        const int c = lane + G * v;
         if (c < N) {
             lds[sp.C + c] = x.rho * yw[v];
             lds[sp.G + c] = th[v].hRT - th[v].sR;
@@ -125,16 +167,16 @@ __device__ __forceinline__ Mix<> mixture_v(const DevMech &m, const DevSparse &sp
 }
 
 // f(y): dY_k/dt and dT/dt, VPL components per lane (0 beyond N).
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ void rhs_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&y)[VPL], double p,
                       const double *dlnA, int lane, double (&f)[VPL])
 {
     const int N = m.N, R = m.R;
     Thermo<> th[VPL];
-    const Mix<> x = mixture_v<VPL>(m, sp, lds, y, p, th, lane);
+    const Mix<> x = mixture_v<VPL, G>(m, sp, lds, y, p, th, lane);
     __syncthreads();
 #pragma unroll 1
-    for (int j = lane; j < R; j += WAVE) {
+    for (int j = lane; j < R; j += G) {
         const RxRec rr = load_rec(m, j);
         const double dl = dlnA ? dlnA[rr.orig] : 0.0;
         const RxOut<> o = reaction<false>(m, lds, rr, x, dl, sp.C, sp.G, sp.H);
@@ -148,7 +190,7 @@ __device__ void rhs_v(const DevMech &m, const DevSparse &sp, double *lds, const 
     double hw[VPL];
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int c = lane + 64 * v;
+        const int c = lane + G * v;
         f[v] = hw[v] = 0.0;
         if (c < N) {
             const double wd = lds[sp.WD + c];
@@ -156,10 +198,10 @@ __device__ void rhs_v(const DevMech &m, const DevSparse &sp, double *lds, const 
             hw[v] = (m.cv ? th[v].hRT - 1.0 : th[v].hRT) * wd;
         }
     }
-    const double fT = -m.Rgas * x.T * vsum<VPL>(hw) / (x.rho * x.cp);
+    const double fT = -m.Rgas * x.T * vsum<VPL, G>(hw) / (x.rho * x.cp);
 #pragma unroll
     for (int v = 0; v < VPL; ++v)
-        if (lane + 64 * v == N) f[v] = fT;
+        if (lane + G * v == N) f[v] = fT;
     __syncthreads();
 }
 
@@ -168,20 +210,20 @@ __device__ void rhs_v(const DevMech &m, const DevSparse &sp, double *lds, const 
 // -nu dq/dT into the species rows and the reaction-enthalpy-weighted
 // derivatives into the temperature row; the border entries are finished per
 // state component after one barrier.
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&y)[VPL], double p,
                       const double *dlnA, int lane, double inv_hg, double (&f)[VPL])
 {
     const int N = m.N, R = m.R;
     double *E = lds + sp.E;
     Thermo<> th[VPL];
-    const Mix<> x = mixture_v<VPL>(m, sp, lds, y, p, th, lane);
+    const Mix<> x = mixture_v<VPL, G>(m, sp, lds, y, p, th, lane);
 #pragma unroll 4
-    for (int e = lane; e < sp.nnz; e += WAVE) E[e] = 0.0;
+    for (int e = lane; e < sp.nnz; e += G) E[e] = 0.0;
     __syncthreads();
     const double RT = m.Rgas * x.T;
 #pragma unroll 1
-    for (int j = lane; j < R; j += WAVE) {
+    for (int j = lane; j < R; j += G) {
         const RxRec rr = load_rec(m, j);
         uint16_t ix[sc::RXI_SIZE];
         __builtin_memcpy(ix, sp.rxi + (size_t)j * sc::RXI_SIZE, sizeof ix);
@@ -223,7 +265,7 @@ __device__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const 
     double hw[VPL], eu[VPL], cpf[VPL], dcp[VPL];
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int c = lane + 64 * v;
+        const int c = lane + G * v;
         f[v] = hw[v] = eu[v] = cpf[v] = dcp[v] = 0.0;
         if (c < N) {
             const double Wk = m.W()[c], iw = m.invW()[c];
@@ -235,10 +277,10 @@ __device__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const 
             dcp[v] = th[v].dcpR * y[v] * iw;
         }
     }
-    const double H = RT * vsum<VPL>(hw);
-    const double Eu = m.cv ? 0.0 : RT * vsum<VPL>(eu);
-    const double Scpf = m.Rgas * vsum<VPL>(cpf);
-    const double Sdcp = m.Rgas * vsum<VPL>(dcp);
+    const double H = RT * vsum<VPL, G>(hw);
+    const double Eu = m.cv ? 0.0 : RT * vsum<VPL, G>(eu);
+    const double Scpf = m.Rgas * vsum<VPL, G>(cpf);
+    const double Sdcp = m.Rgas * vsum<VPL, G>(dcp);
     const double fT = -H / (x.rho * x.cp);
     const double vs = m.cv ? 1.0 : x.Wbar;
     const double ct = m.cv ? 0.0 : x.invT;
@@ -246,7 +288,7 @@ __device__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const 
     const double icp = 1.0 / x.cp;
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int c = lane + 64 * v;
+        const int c = lane + G * v;
         if (c < N) {
             const int32_t *cm = sp.comp + CMP * c;
             const double us = m.cv ? lds[sp.UA + c] : lds[sp.UA + c] / x.rho;
@@ -273,38 +315,19 @@ __device__ __forceinline__ int lo16(uint64_t x) { return (int)(x & 0xffff); }
 __device__ __forceinline__ int mid16(uint64_t x) { return (int)((x >> 16) & 0xffff); }
 __device__ __forceinline__ int hi16(uint64_t x) { return (int)((x >> 32) & 0xffff); }
 
-// Items [q0, q1) of an update phase: target -= value(a) * value(b), with the
-// target/a/b LDS indices taken from each item by TA/TB/TC (entries or vector
-// positions), four 64-item groups in flight.
-template <class F>
-__device__ __forceinline__ void run_items(const uint64_t *items, int q0, int q1, int lane, F op)
-{
-#pragma unroll 1
-    for (int base = q0; base < q1; base += 4 * WAVE) {  // uniform trip count across the wave
-        uint64_t it[4];
-        bool ok[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int q = base + u * WAVE + lane;
-            ok[u] = q < q1;
-            it[u] = ok[u] ? items[q] : 0;
-        }
-        op(it, ok);
-    }
-}
-
-// The first four 64-item groups of a phase, loaded ahead (the loads of the
+// The first four G-item groups of a phase, loaded ahead (the loads of the
 // next phase are issued before the current one is processed, so their
 // latency overlaps its LDS work).
 struct Pre {
     uint64_t it[4];
 };
+template <int G>
 __device__ __forceinline__ Pre preload(const uint64_t *items, int q0, int q1, int lane)
 {
     Pre p;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const int q = q0 + u * WAVE + lane;
+        const int q = q0 + u * G + lane;
         p.it[u] = q < q1 ? items[q] : ~0ull;
     }
     return p;
@@ -342,62 +365,42 @@ __device__ __forceinline__ void lu_update_items(double *E, const uint64_t (&it)[
 
 // Numeric LU of the formed matrix in E by the static level schedule, then
 // dinv = 1/u_kk and the rows of U scaled to a unit diagonal.
+template <int G>
 __device__ void lu_v(const DevSparse &sp, double *lds, int lane)
 {
     double *E = lds + sp.E;
     double *DINV = lds + sp.DINV;
-    Pre pre = preload(sp.lu_b, sp.lu_b_lvl[0], sp.lu_b_lvl[1], lane);
+    Pre pre = preload<G>(sp.lu_b, sp.lu_b_lvl[0], sp.lu_b_lvl[1], lane);
 #pragma unroll 1
     for (int l = 0; l < sp.nl_lu; ++l) {
         const int b0 = sp.lu_b_lvl[l], b1 = sp.lu_b_lvl[l + 1];
         const int c0 = sp.lu_c_lvl[l], c1 = sp.lu_c_lvl[l + 1];
         Pre cur = pre;
-        pre = preload(sp.lu_c, c0, c1, lane);
+        pre = preload<G>(sp.lu_c, c0, c1, lane);
         lu_scale_items(E, cur.it);
 #pragma unroll 1
-        for (int base = b0 + 4 * WAVE; base < b1; base += 4 * WAVE)
-            lu_scale_items(E, preload(sp.lu_b, base, b1, lane).it);
+        for (int base = b0 + 4 * G; base < b1; base += 4 * G)
+            lu_scale_items(E, preload<G>(sp.lu_b, base, b1, lane).it);
         __syncthreads();
         cur = pre;
-        if (l + 1 < sp.nl_lu) pre = preload(sp.lu_b, b1, sp.lu_b_lvl[l + 2], lane);
+        if (l + 1 < sp.nl_lu) pre = preload<G>(sp.lu_b, b1, sp.lu_b_lvl[l + 2], lane);
         if (c1 > c0) {
             lu_update_items(E, cur.it);
 #pragma unroll 1
-            for (int base = c0 + 4 * WAVE; base < c1; base += 4 * WAVE)
-                lu_update_items(E, preload(sp.lu_c, base, c1, lane).it);
+            for (int base = c0 + 4 * G; base < c1; base += 4 * G)
+                lu_update_items(E, preload<G>(sp.lu_c, base, c1, lane).it);
             __syncthreads();
         }
     }
 #pragma unroll 1
-    for (int k = lane; k < sp.n; k += WAVE) DINV[k] = 1.0 / E[sp.diag[k]];
+    for (int k = lane; k < sp.n; k += G) DINV[k] = 1.0 / E[sp.diag[k]];
     __syncthreads();
 #pragma unroll 2
-    for (int q = lane; q < sp.n_u; q += WAVE) {
+    for (int q = lane; q < sp.n_u; q += G) {
         const uint32_t it = sp.lu_u[q];
         E[it & 0xffff] *= DINV[it >> 16];
     }
     __syncthreads();
-}
-
-// one sweep of a triangular solve: x_i -= E[e] x_p, level by level
-__device__ __forceinline__ void sweep(const double *E, double *X, const int *lvl, const uint64_t *items, int nl,
-                                      int lane)
-{
-#pragma unroll 1
-    for (int l = 0; l < nl; ++l) {
-        run_items(items, lvl[l], lvl[l + 1], lane, [&](const uint64_t (&it)[4], const bool (&ok)[4]) {
-            double a[4], b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = ok[u] ? E[hi16(it[u])] : 0.0;
-                b[u] = ok[u] ? X[mid16(it[u])] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (ok[u]) atomicAdd(&X[lo16(it[u])], -a[u] * b[u]);
-        });
-        __syncthreads();
-    }
 }
 
 // Solve M x = b with the factors in E (b, x: VPL components per lane).
@@ -409,41 +412,46 @@ __device__ __forceinline__ void sweep(const double *E, double *X, const int *lvl
 // entries in the rows above it: a count of the column's row mask below the
 // lane (mbcnt), with the mask and start read as wave-uniform values.  No
 // barrier and no per-lane index load inside the sweeps.
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ __forceinline__ double rd_pos(const double (&z)[VPL], int k)
 {
-    if (VPL == 1 || k < 64) return rdlane(z[0], k);
-    return rdlane(z[VPL - 1], k - 64);
+    if (VPL == 1 || k < 64) return gbcast<G>(z[0], k);
+    return gbcast<G>(z[VPL - 1], k - 64);
 }
 
-// lanes below this one that are set in m
-__device__ __forceinline__ int below(uint64_t m)
+// bits of m below this lane's position in its group (mbcnt for a whole wave)
+template <int G>
+__device__ __forceinline__ int below(uint64_t m, int lane)
 {
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if constexpr (G == WAVE)
+        return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    else
+        return __builtin_popcountll(m & ((1ull << lane) - 1));
 }
 
-__device__ __forceinline__ uint64_t rdlane64(uint64_t v, int lane)
+template <int G>
+__device__ __forceinline__ uint64_t gbcast64(uint64_t v, int k)
 {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    const uint32_t lo = (uint32_t)gbcast_i<G>((int)(uint32_t)v, k);
+    const uint32_t hi = (uint32_t)gbcast_i<G>((int)(uint32_t)(v >> 32), k);
     return (uint64_t)hi << 32 | lo;
 }
 
 // The columns' row masks and entry starts, held one column per lane
 // (column lane + 64 w in slot w), loaded once per solve.
-template <int VPL>
+template <int VPL, int G = WAVE>
 struct ColMeta {
     uint64_t m0[VPL], m1[VPL];
     int start[VPL];
 };
 
-template <int VPL>
-__device__ __forceinline__ ColMeta<VPL> col_meta(const DevSparse &sp, int lane)
+template <int VPL, int G = WAVE>
+__device__ __forceinline__ ColMeta<VPL, G> col_meta(const DevSparse &sp, int lane)
 {
-    ColMeta<VPL> c;
+    ColMeta<VPL, G> c;
 #pragma unroll
     for (int w = 0; w < VPL; ++w) {
-        const int k = lane + 64 * w;
+        const int k = lane + G * w;
         const bool ok = k < sp.n;
         c.m0[w] = ok ? sp.cmask[2 * k] : 0;
         c.m1[w] = ok && VPL > 1 ? sp.cmask[2 * k + 1] : 0;
@@ -456,21 +464,21 @@ __device__ __forceinline__ ColMeta<VPL> col_meta(const DevSparse &sp, int lane)
 // no entry there).  An absent entry's index still lies inside the LDS
 // allocation (at most the column's end), and the select keeps whatever it
 // holds out of the result.
-template <int VPL>
-__device__ __forceinline__ void col_values(const ColMeta<VPL> &c, const double *E, int k, int lane,
+template <int VPL, int G = WAVE>
+__device__ __forceinline__ void col_values(const ColMeta<VPL, G> &c, const double *E, int k, int lane,
                                            double (&val)[VPL])
 {
     const int w = VPL == 1 ? 0 : k >> 6, kk = k & 63;
-    const uint64_t m0 = rdlane64(c.m0[w], kk);
-    const int base = __builtin_amdgcn_readlane(c.start[w], kk);
-    val[0] = (m0 >> lane) & 1 ? E[base + below(m0)] : 0.0;
+    const uint64_t m0 = gbcast64<G>(c.m0[w], kk);
+    const int base = gbcast_i<G>(c.start[w], kk);
+    val[0] = (m0 >> lane) & 1 ? E[base + below<G>(m0, lane)] : 0.0;
     if (VPL > 1) {
-        const uint64_t m1 = rdlane64(c.m1[w], kk);
-        val[VPL - 1] = (m1 >> lane) & 1 ? E[base + __builtin_popcountll(m0) + below(m1)] : 0.0;
+        const uint64_t m1 = gbcast64<G>(c.m1[w], kk);
+        val[VPL - 1] = (m1 >> lane) & 1 ? E[base + __builtin_popcountll(m0) + below<G>(m1, lane)] : 0.0;
     }
 }
 
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&b)[VPL], int lane,
                         double (&x)[VPL])
 {
@@ -478,10 +486,10 @@ __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, cons
     const double *E = lds + sp.E;
     double *X = lds + sp.X;
     const double *DINV = lds + sp.DINV;
-    const ColMeta<VPL> cm = col_meta<VPL>(sp, lane);
+    const ColMeta<VPL, G> cm = col_meta<VPL, G>(sp, lane);
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int c = lane + 64 * v;
+        const int c = lane + G * v;
         if (c < N) X[sp.comp[CMP * c]] = b[v] * m.invW()[c];
         if (c == N) X[sp.comp[CMP * N]] = b[v];
     }
@@ -490,49 +498,49 @@ __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, cons
     double z[VPL];
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int q = lane + 64 * v;
+        const int q = lane + G * v;
         z[v] = q < n ? X[q] : 0.0;
     }
     // forward: x_i -= l_ik x_k, k ascending, rows below the diagonal (the
     // next column's values are read while this one is applied)
     double nxt[VPL], cur[VPL];
-    col_values<VPL>(cm, E, 0, lane, nxt);
+    col_values<VPL, G>(cm, E, 0, lane, nxt);
     for (int k = 0; k < n - 1; ++k) {
 #pragma unroll
         for (int v = 0; v < VPL; ++v) cur[v] = nxt[v];
-        if (k + 1 < n - 1) col_values<VPL>(cm, E, k + 1, lane, nxt);
-        const double zk = rd_pos<VPL>(z, k);
+        if (k + 1 < n - 1) col_values<VPL, G>(cm, E, k + 1, lane, nxt);
+        const double zk = rd_pos<VPL, G>(z, k);
 #pragma unroll
         for (int v = 0; v < VPL; ++v)
-            if (lane + 64 * v > k) z[v] = fma(-cur[v], zk, z[v]);
+            if (lane + G * v > k) z[v] = fma(-cur[v], zk, z[v]);
     }
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int q = lane + 64 * v;
+        const int q = lane + G * v;
         if (q < n) z[v] *= DINV[q];
     }
     // backward with the unit-diagonal U: x_i -= u'_ik x_k, k descending,
     // rows above the diagonal
-    col_values<VPL>(cm, E, n - 1, lane, nxt);
+    col_values<VPL, G>(cm, E, n - 1, lane, nxt);
     for (int k = n - 1; k > 0; --k) {
 #pragma unroll
         for (int v = 0; v < VPL; ++v) cur[v] = nxt[v];
-        if (k > 1) col_values<VPL>(cm, E, k - 1, lane, nxt);
-        const double zk = rd_pos<VPL>(z, k);
+        if (k > 1) col_values<VPL, G>(cm, E, k - 1, lane, nxt);
+        const double zk = rd_pos<VPL, G>(z, k);
 #pragma unroll
         for (int v = 0; v < VPL; ++v)
-            if (lane + 64 * v < k) z[v] = fma(-cur[v], zk, z[v]);
+            if (lane + G * v < k) z[v] = fma(-cur[v], zk, z[v]);
     }
     __syncthreads();  // every lane has read X
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int q = lane + 64 * v;
+        const int q = lane + G * v;
         if (q < n) X[q] = z[v];
     }
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int c = lane + 64 * v;
+        const int c = lane + G * v;
         x[v] = c < N ? X[sp.comp[CMP * c]] * m.W()[c] : c == N ? X[sp.comp[CMP * N]] : 0.0;
     }
     __syncthreads();
@@ -541,7 +549,7 @@ __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, cons
 // ---------------------------------------------------------------------------
 // one Rosenbrock attempt and the integration of a cell
 // ---------------------------------------------------------------------------
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ void ros_attempt_v(const DevMech &m, const DevSparse &sp, const Opts &o, double *lds,
                               const double (&y)[VPL], double p, const double *dlnA, int lane, double hc, double *err,
                               double (&ynew)[VPL])
@@ -550,8 +558,8 @@ __device__ void ros_attempt_v(const DevMech &m, const DevSparse &sp, const Opts 
     double *U = lds + sp.U;
     const int NV = sp.NV;
     double f0[VPL], flast[VPL];
-    jac_v<VPL>(m, sp, lds, y, p, dlnA, lane, 1.0 / (GAM * hc), f0);
-    lu_v(sp, lds, lane);
+    jac_v<VPL, G>(m, sp, lds, y, p, dlnA, lane, 1.0 / (GAM * hc), f0);
+    lu_v<G>(sp, lds, lane);
     const double ih = 1.0 / hc;
 #pragma unroll
     for (int v = 0; v < VPL; ++v) flast[v] = f0[v];
@@ -570,21 +578,21 @@ __device__ void ros_attempt_v(const DevMech &m, const DevSparse &sp, const Opts 
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
                 ys[v] = y[v];
-                for (int j = 0; j < i; ++j) ys[v] += TA[i][j] * U[j * NV + lane + 64 * v];
+                for (int j = 0; j < i; ++j) ys[v] += TA[i][j] * U[j * NV + lane + G * v];
             }
-            rhs_v<VPL>(m, sp, lds, ys, p, dlnA, lane, fi);
+            rhs_v<VPL, G>(m, sp, lds, ys, p, dlnA, lane, fi);
 #pragma unroll
             for (int v = 0; v < VPL; ++v) flast[v] = fi[v];
         }
         double ui[VPL];
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
-            for (int j = 0; j < i; ++j) fi[v] += (TC[i][j] * ih) * U[j * NV + lane + 64 * v];
-            if (lane + 64 * v >= n) fi[v] = 0.0;
+            for (int j = 0; j < i; ++j) fi[v] += (TC[i][j] * ih) * U[j * NV + lane + G * v];
+            if (lane + G * v >= n) fi[v] = 0.0;
         }
-        solve_v<VPL>(m, sp, lds, fi, lane, ui);
+        solve_v<VPL, G>(m, sp, lds, fi, lane, ui);
 #pragma unroll
-        for (int v = 0; v < VPL; ++v) U[i * NV + lane + 64 * v] = ui[v];
+        for (int v = 0; v < VPL; ++v) U[i * NV + lane + G * v] = ui[v];
     }
     double e2[VPL];
 #pragma unroll
@@ -592,22 +600,22 @@ __device__ void ros_attempt_v(const DevMech &m, const DevSparse &sp, const Opts 
         double yn = y[v], ev = 0.0;
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-            const double ui = U[i * NV + lane + 64 * v];
+            const double ui = U[i * NV + lane + G * v];
             yn += TM[i] * ui;
             ev += TE[i] * ui;
         }
         ynew[v] = yn;
         e2[v] = 0.0;
-        if (lane + 64 * v < n) {
+        if (lane + G * v < n) {
             const double sc = o.atol + o.rtol * fmax(fabs(y[v]), fabs(yn));
             const double r = ev / sc;
             e2[v] = r * r;
         }
     }
-    *err = sqrt(vsum<VPL>(e2) / n);
+    *err = sqrt(vsum<VPL, G>(e2) / n);
 }
 
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ int advance_v(const DevMech &m, const DevSparse &sp, const Opts &o, double *lds, double (&y)[VPL],
                          double p, double dt, const double *dlnA, int lane, Ctl &s)
 {
@@ -618,7 +626,7 @@ __device__ int advance_v(const DevMech &m, const DevSparse &sp, const Opts &o, d
         const int st = ctl_begin(s, o, dt, hc, last);
         if (st != SC_CELL_OK) return st;
         double err, ynew[VPL];
-        ros_attempt_v<VPL>(m, sp, o, lds, y, p, dlnA, lane, hc, &err, ynew);
+        ros_attempt_v<VPL, G>(m, sp, o, lds, y, p, dlnA, lane, hc, &err, ynew);
         const int r = ctl_end(s, o, err, hc, last, dt);
         if (r < 0) return -r;
         if (r == 1) {
@@ -629,18 +637,18 @@ __device__ int advance_v(const DevMech &m, const DevSparse &sp, const Opts &o, d
     }
 }
 
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ __forceinline__ bool bad_input_v(const DevMech &m, const double (&y)[VPL], double p, double dt, int lane)
 {
     bool bad = false;
 #pragma unroll
-    for (int v = 0; v < VPL; ++v) bad = bad || (lane + 64 * v <= m.N && !isfinite(y[v]));
-    const double T = comp_T<VPL>(m, y);
-    return __any(bad) || !(T > 0.0) || !isfinite(T) || !(p > 0.0) || !isfinite(p) || !(dt >= 0.0) ||
+    for (int v = 0; v < VPL; ++v) bad = bad || (lane + G * v <= m.N && !isfinite(y[v]));
+    const double T = comp_T<VPL, G>(m, y);
+    return gany<G>(bad) || !(T > 0.0) || !isfinite(T) || !(p > 0.0) || !isfinite(p) || !(dt >= 0.0) ||
            !isfinite(dt);
 }
 
-template <int VPL>
+template <int VPL, int G = WAVE>
 __device__ void integrate_cell_v(const DevMech &m, const DevSparse &sp, const Opts &o, double *lds, int64_t c,
                                  int lane, const double *T0, const double *P, const double *Y0, int64_t ld,
                                  const double *DT, const double *dlnA, double *h_io, double *T1, double *Y1,
@@ -649,16 +657,16 @@ __device__ void integrate_cell_v(const DevMech &m, const DevSparse &sp, const Op
     // a cell mapped onto another cell's result is left to the mapping pass
     if (ref && ref[c] != c) return;
     double y[VPL];
-    load_state_v<VPL>(m, T0, Y0, ld, c, lane, y);
+    load_state_v<VPL, G>(m, T0, Y0, ld, c, lane, y);
     const double p = P[c], dt = DT[c];
     int st = SC_CELL_OK;
     Ctl s = ctl_init(initial_step(h_io, c, dt), dt);
-    if (bad_input_v<VPL>(m, y, p, dt, lane)) {
+    if (bad_input_v<VPL, G>(m, y, p, dt, lane)) {
         st = SC_CELL_BAD_INPUT;
     } else if (dt > 0.0) {
-        st = advance_v<VPL>(m, sp, o, lds, y, p, dt, dlnA, lane, s);
+        st = advance_v<VPL, G>(m, sp, o, lds, y, p, dt, dlnA, lane, s);
     }
-    store_state_v<VPL>(m, T1, Y1, ld, c, lane, y);
+    store_state_v<VPL, G>(m, T1, Y1, ld, c, lane, y);
     if (lane == 0) {
         status[c] = st;
         if (nacc_out) nacc_out[c] = s.nacc;
@@ -677,7 +685,15 @@ __device__ void integrate_cell_v(const DevMech &m, const DevSparse &sp, const Op
 // loops; measured on the 53-species batch it is still 1.6x faster than one
 // wave per SIMD.
 #define SP_OCC __attribute__((amdgpu_waves_per_eu(VPL == 1 ? 2 : 1, VPL == 1 ? 2 : 1)))
-template <int VPL, bool CV>
+// CPW cells per wave: each cell takes G = 64 / CPW lanes and its own LDS
+// region (sp.size doubles); lane = threadIdx.x % G, group = threadIdx.x / G.
+#define SP_GEOMETRY                                   \
+    constexpr int G = WAVE / CPW;                     \
+    const int lane = (int)threadIdx.x % G;            \
+    const int grp = (int)threadIdx.x / G;             \
+    double *ldsg = lds + (size_t)grp * sp.size;
+
+template <int VPL, bool CV, int CPW>
 __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp(DevMech mk, DevSparse sp, Opts o, int64_t n,
                                                        const double *T0, const double *P, const double *Y0,
                                                        int64_t ld, const double *DT, const double *dlnA,
@@ -686,12 +702,16 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp(DevMech mk, DevSpa
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
-    const int64_t c = blockIdx.x;
+    SP_GEOMETRY
+    const int64_t c = (int64_t)blockIdx.x * CPW + grp;
     if (c >= n) return;
-    integrate_cell_v<VPL>(m, sp, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej, ref);
+    integrate_cell_v<VPL, G>(m, sp, o, ldsg, c, lane, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc, nrej,
+                             ref);
 }
 
-template <int VPL, bool CV>
+// Each pull takes tile * CPW queue positions; the wave's groups take them
+// CPW at a time (a group whose position is past the end idles).
+template <int VPL, bool CV, int CPW>
 __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_persistent(DevMech mk, DevSparse sp, Opts o, int64_t n,
                                                                   const double *T0, const double *P,
                                                                   const double *Y0, int64_t ld, const double *DT,
@@ -702,24 +722,27 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_persistent(DevMech
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
-    const int lane = threadIdx.x;
+    SP_GEOMETRY
 #pragma unroll 1
     while (true) {
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(queue, (unsigned long long)tile);
+        if (threadIdx.x == 0) base = atomicAdd(queue, (unsigned long long)tile * CPW);
         base = __shfl(base, 0, WAVE);
         if (base >= (unsigned long long)n) break;
-        const int64_t end = min((int64_t)base + tile, n);
+        const int64_t end = min((int64_t)base + (int64_t)tile * CPW, n);
 #pragma unroll 1
-        for (int64_t i = (int64_t)base; i < end; ++i) {
-            const int64_t c = perm ? (int64_t)perm[i] : i;
-            integrate_cell_v<VPL>(m, sp, o, lds, c, lane, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc,
-                                  nrej, ref);
+        for (int64_t i = (int64_t)base; i < end; i += CPW) {
+            const int64_t q = i + grp;
+            if (q < end) {
+                const int64_t c = perm ? (int64_t)perm[q] : q;
+                integrate_cell_v<VPL, G>(m, sp, o, ldsg, c, lane, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status,
+                                         nacc, nrej, ref);
+            }
         }
     }
 }
 
-template <int VPL, bool CV>
+template <int VPL, bool CV, int CPW>
 __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_static(DevMech mk, DevSparse sp, Opts o, int64_t n,
                                                               const double *T0, const double *P, const double *Y0,
                                                               int64_t ld, const double *DT, const double *dlnA,
@@ -729,28 +752,29 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_static(DevMech mk,
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
+    SP_GEOMETRY
     const int64_t c0 = (int64_t)blockIdx.x * group;
     const int64_t c1 = min(c0 + group, n);
 #pragma unroll 1
-    for (int64_t c = c0; c < c1; ++c)
-        integrate_cell_v<VPL>(m, sp, o, lds, c, threadIdx.x, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc,
-                              nrej, ref);
+    for (int64_t c = c0 + grp; c < c1; c += CPW)
+        integrate_cell_v<VPL, G>(m, sp, o, ldsg, c, lane, T0, P, Y0, ld, DT, dlnA, h_io, T1, Y1, status, nacc,
+                                 nrej, ref);
 }
 
-template <int VPL, bool CV>
+template <int VPL, bool CV, int CPW>
 __global__ void __launch_bounds__(WAVE) k_rhs_sp(DevMech mk, DevSparse sp, int64_t n, const double *T,
                                                  const double *P, const double *Y, int64_t ld, const double *dlnA,
                                                  double *fT, double *fY)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
-    const int lane = threadIdx.x;
-    const int64_t c = blockIdx.x;
+    SP_GEOMETRY
+    const int64_t c = (int64_t)blockIdx.x * CPW + grp;
     if (c >= n) return;
     double y[VPL], f[VPL];
-    load_state_v<VPL>(m, T, Y, ld, c, lane, y);
-    rhs_v<VPL>(m, sp, lds, y, P[c], dlnA, lane, f);
-    store_state_v<VPL>(m, fT, fY, ld, c, lane, f);
+    load_state_v<VPL, G>(m, T, Y, ld, c, lane, y);
+    rhs_v<VPL, G>(m, sp, ldsg, y, P[c], dlnA, lane, f);
+    store_state_v<VPL, G>(m, fT, fY, ld, c, lane, f);
 }
 
 // The Jacobian J (dense output, [c][i][j] over (Y, T)) recovered from the
@@ -758,20 +782,20 @@ __global__ void __launch_bounds__(WAVE) k_rhs_sp(DevMech mk, DevSparse sp, int64
 // sigma border): eliminating sigma, M'_ij = A_ij + A_i,sigma A_sigma,j, and
 // undoing the scaling, J_ij = -(W_i / W_j) M'_ij (species i, j), J_iT =
 // -W_i A_iT, J_Tj = -A_Tj / W_j, J_TT = -A_TT.
-template <int VPL, bool CV>
+template <int VPL, bool CV, int CPW>
 __global__ void __launch_bounds__(WAVE) k_jac_sp(DevMech mk, DevSparse sp, int64_t n, const double *T,
                                                  const double *P, const double *Y, int64_t ld, const double *dlnA,
                                                  double *J)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
-    const int lane = threadIdx.x;
-    const int64_t c = blockIdx.x;
+    SP_GEOMETRY
+    const int64_t c = (int64_t)blockIdx.x * CPW + grp;
     if (c >= n) return;
     double y[VPL], f[VPL];
-    load_state_v<VPL>(m, T, Y, ld, c, lane, y);
-    jac_v<VPL>(m, sp, lds, y, P[c], dlnA, lane, 0.0, f);
-    const double *E = lds + sp.E;
+    load_state_v<VPL, G>(m, T, Y, ld, c, lane, y);
+    jac_v<VPL, G>(m, sp, ldsg, y, P[c], dlnA, lane, 0.0, f);
+    const double *E = ldsg + sp.E;
     const int N = m.N, nn = N + 1, ns = sp.n;
     const int pS = ns - 1;
     auto A = [&](int pi, int pj) {
@@ -779,7 +803,7 @@ __global__ void __launch_bounds__(WAVE) k_jac_sp(DevMech mk, DevSparse sp, int64
         return e == sc::NOENT ? 0.0 : E[e];
     };
 #pragma unroll 1
-    for (int q = lane; q < nn * nn; q += WAVE) {
+    for (int q = lane; q < nn * nn; q += G) {
         const int i = q / nn, j = q % nn;
         const int pi = sp.comp[CMP * i], pj = sp.comp[CMP * j];  // comp[CMP * N] is pos_T
         double val;
@@ -791,7 +815,7 @@ __global__ void __launch_bounds__(WAVE) k_jac_sp(DevMech mk, DevSparse sp, int64
     }
 }
 
-template <int VPL, bool CV>
+template <int VPL, bool CV, int CPW>
 __global__ void __launch_bounds__(WAVE) k_linsolve_sp(DevMech mk, DevSparse sp, int64_t n, const double *T,
                                                       const double *P, const double *Y, int64_t ld,
                                                       const double *dlnA, const double *hg, const double *b,
@@ -799,23 +823,23 @@ __global__ void __launch_bounds__(WAVE) k_linsolve_sp(DevMech mk, DevSparse sp, 
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
-    const int lane = threadIdx.x;
-    const int64_t c = blockIdx.x;
+    SP_GEOMETRY
+    const int64_t c = (int64_t)blockIdx.x * CPW + grp;
     if (c >= n) return;
     double y[VPL], f[VPL], bb[VPL], xx[VPL];
-    load_state_v<VPL>(m, T, Y, ld, c, lane, y);
-    jac_v<VPL>(m, sp, lds, y, P[c], dlnA, lane, 1.0 / hg[c], f);
-    lu_v(sp, lds, lane);
+    load_state_v<VPL, G>(m, T, Y, ld, c, lane, y);
+    jac_v<VPL, G>(m, sp, ldsg, y, P[c], dlnA, lane, 1.0 / hg[c], f);
+    lu_v<G>(sp, ldsg, lane);
     const int nn = m.N + 1;
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int i = lane + 64 * v;
+        const int i = lane + G * v;
         bb[v] = i < nn ? b[c * nn + i] : 0.0;
     }
-    solve_v<VPL>(m, sp, lds, bb, lane, xx);
+    solve_v<VPL, G>(m, sp, ldsg, bb, lane, xx);
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        const int i = lane + 64 * v;
+        const int i = lane + G * v;
         if (i < nn) x[c * nn + i] = xx[v];
     }
 }
@@ -823,46 +847,49 @@ __global__ void __launch_bounds__(WAVE) k_linsolve_sp(DevMech mk, DevSparse sp, 
 // ---------------------------------------------------------------------------
 // launchers (host)
 // ---------------------------------------------------------------------------
-#define SP_KERNEL(k) k<VPLV, CVV>
-#define SP_DISPATCH(vpl, cv, ...)                                                        \
-    if ((vpl) == 1) {                                                                    \
-        constexpr int VPLV = 1;                                                          \
-        if (cv) { constexpr bool CVV = true; __VA_ARGS__; }                             \
-        else { constexpr bool CVV = false; __VA_ARGS__; }                               \
-    } else if ((vpl) == 2) {                                                             \
-        constexpr int VPLV = 2;                                                          \
-        if (cv) { constexpr bool CVV = true; __VA_ARGS__; }                             \
-        else { constexpr bool CVV = false; __VA_ARGS__; }                               \
-    } else {                                                                             \
-        return hipErrorInvalidValue;                                                     \
+#define SP_KERNEL(k) k<VPLV, CVV, CPWV>
+#define SP_CASE(vplv, cpwv, ...)                                                                 \
+    if (vpl == (vplv) && cpw == (cpwv)) {                                                        \
+        constexpr int VPLV = vplv, CPWV = cpwv;                                                  \
+        if (m.cv) { constexpr bool CVV = true; __VA_ARGS__; }                                   \
+        else { constexpr bool CVV = false; __VA_ARGS__; }                                       \
+        return hipGetLastError();                                                                \
     }
+#define SP_DISPATCH(...)                   \
+    SP_CASE(1, 1, __VA_ARGS__)             \
+    SP_CASE(1, 2, __VA_ARGS__)             \
+    SP_CASE(1, 4, __VA_ARGS__)             \
+    SP_CASE(2, 1, __VA_ARGS__)             \
+    return hipErrorInvalidValue;
 
-static size_t sp_lds(const DevSparse &sp) { return sizeof(double) * (size_t)sp.size; }
+// LDS of one workgroup: one region of sp.size doubles per cell of the wave
+static size_t sp_lds(const DevSparse &sp, int cpw) { return sizeof(double) * (size_t)sp.size * cpw; }
+static unsigned sp_blocks(int64_t n, int cpw) { return (unsigned)((n + cpw - 1) / cpw); }
 
 hipError_t launch_rhs_sp(int vpl, const DevMech &m, const DevSparse &sp, int64_t n, const double *T,
                          const double *p, const double *Y, int64_t ld, const double *dlnA, double *fT, double *fY,
                          hipStream_t s)
 {
-    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_rhs_sp), dim3((unsigned)n), dim3(WAVE), sp_lds(sp), s, m,
-                                               sp, n, T, p, Y, ld, dlnA, fT, fY));
-    return hipGetLastError();
+    const int cpw = sp.cpw;
+    SP_DISPATCH(hipLaunchKernelGGL(SP_KERNEL(k_rhs_sp), dim3(sp_blocks(n, cpw)), dim3(WAVE), sp_lds(sp, cpw), s, m,
+                                   sp, n, T, p, Y, ld, dlnA, fT, fY))
 }
 
 hipError_t launch_jac_sp(int vpl, const DevMech &m, const DevSparse &sp, int64_t n, const double *T,
                          const double *p, const double *Y, int64_t ld, const double *dlnA, double *J, hipStream_t s)
 {
-    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_jac_sp), dim3((unsigned)n), dim3(WAVE), sp_lds(sp), s, m,
-                                               sp, n, T, p, Y, ld, dlnA, J));
-    return hipGetLastError();
+    const int cpw = sp.cpw;
+    SP_DISPATCH(hipLaunchKernelGGL(SP_KERNEL(k_jac_sp), dim3(sp_blocks(n, cpw)), dim3(WAVE), sp_lds(sp, cpw), s, m,
+                                   sp, n, T, p, Y, ld, dlnA, J))
 }
 
 hipError_t launch_linsolve_sp(int vpl, const DevMech &m, const DevSparse &sp, int64_t n, const double *T,
                               const double *p, const double *Y, int64_t ld, const double *dlnA, const double *hg,
                               const double *b, double *x, hipStream_t s)
 {
-    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_linsolve_sp), dim3((unsigned)n), dim3(WAVE), sp_lds(sp),
-                                               s, m, sp, n, T, p, Y, ld, dlnA, hg, b, x));
-    return hipGetLastError();
+    const int cpw = sp.cpw;
+    SP_DISPATCH(hipLaunchKernelGGL(SP_KERNEL(k_linsolve_sp), dim3(sp_blocks(n, cpw)), dim3(WAVE), sp_lds(sp, cpw),
+                                   s, m, sp, n, T, p, Y, ld, dlnA, hg, b, x))
 }
 
 hipError_t launch_integrate_sp(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o, int64_t n,
@@ -870,9 +897,9 @@ hipError_t launch_integrate_sp(int vpl, const DevMech &m, const DevSparse &sp, c
                                const double *dlnA, double *h_io, double *T1, double *Y1, int32_t *st, int32_t *na,
                                int32_t *nr, const int32_t *ref, hipStream_t s)
 {
-    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp), dim3((unsigned)n), dim3(WAVE), sp_lds(sp),
-                                               s, m, sp, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, ref));
-    return hipGetLastError();
+    const int cpw = sp.cpw;
+    SP_DISPATCH(hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp), dim3(sp_blocks(n, cpw)), dim3(WAVE), sp_lds(sp, cpw),
+                                   s, m, sp, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, ref))
 }
 
 hipError_t launch_integrate_sp_persistent(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o,
@@ -882,10 +909,10 @@ hipError_t launch_integrate_sp_persistent(int vpl, const DevMech &m, const DevSp
                                           unsigned long long *queue, const int32_t *perm, int tile, int grid,
                                           const int32_t *ref, hipStream_t s)
 {
-    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp_persistent), dim3((unsigned)grid),
-                                               dim3(WAVE), sp_lds(sp), s, m, sp, o, n, T0, p, Y0, ld, dt, dlnA,
-                                               h_io, T1, Y1, st, na, nr, queue, perm, tile, ref));
-    return hipGetLastError();
+    const int cpw = sp.cpw;
+    SP_DISPATCH(hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp_persistent), dim3((unsigned)grid), dim3(WAVE),
+                                   sp_lds(sp, cpw), s, m, sp, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na,
+                                   nr, queue, perm, tile, ref))
 }
 
 hipError_t launch_integrate_sp_static(int vpl, const DevMech &m, const DevSparse &sp, const Opts &o, int64_t n,
@@ -894,12 +921,11 @@ hipError_t launch_integrate_sp_static(int vpl, const DevMech &m, const DevSparse
                                       int32_t *st, int32_t *na, int32_t *nr, int grid, const int32_t *ref,
                                       hipStream_t s)
 {
+    const int cpw = sp.cpw;
     const int64_t group = (n + grid - 1) / grid;
     const unsigned g = (unsigned)((n + group - 1) / group);
-    SP_DISPATCH(vpl, m.cv, hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp_static), dim3(g), dim3(WAVE), sp_lds(sp), s,
-                                               m, sp, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr,
-                                               group, ref));
-    return hipGetLastError();
+    SP_DISPATCH(hipLaunchKernelGGL(SP_KERNEL(k_integrate_sp_static), dim3(g), dim3(WAVE), sp_lds(sp, cpw), s, m,
+                                   sp, o, n, T0, p, Y0, ld, dt, dlnA, h_io, T1, Y1, st, na, nr, group, ref))
 }
 
 int persistent_capacity_sp(int vpl, const DevSparse &sp, int device)
@@ -907,12 +933,12 @@ int persistent_capacity_sp(int vpl, const DevSparse &sp, int device)
     int per_cu = 0, cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
     hipError_t e = hipErrorInvalidValue;
-    if (vpl == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_sp_persistent<1, false>, WAVE,
-                                                         sp_lds(sp));
-    else if (vpl == 2)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrate_sp_persistent<2, false>, WAVE,
-                                                         sp_lds(sp));
+    const int cpw = sp.cpw;
+    auto occ = [&](auto kern) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVE, sp_lds(sp, cpw)); };
+    if (vpl == 1 && cpw == 1) e = occ(k_integrate_sp_persistent<1, false, 1>);
+    else if (vpl == 1 && cpw == 2) e = occ(k_integrate_sp_persistent<1, false, 2>);
+    else if (vpl == 1 && cpw == 4) e = occ(k_integrate_sp_persistent<1, false, 4>);
+    else if (vpl == 2 && cpw == 1) e = occ(k_integrate_sp_persistent<2, false, 1>);
     return e == hipSuccess ? per_cu * cus : 0;
 }
 

