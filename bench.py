@@ -518,6 +518,10 @@ def bench_chained(args):
     Y = torch.tensor(np.ascontiguousarray(c["Y"].T), device=dev)
     dt = torch.tensor(c["dt"], device=dev)
     mech = sc.Mechanism(c["mech"].to_text())
+    if mech.N + 1 <= 64:
+        # with the gradient: the forward and the adjoint's recording pass run
+        # the same (dense) kernels, so the recorded trajectory is the forward's
+        args.linalg = "dense"
     plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, linalg=args.linalg)
     plan.adjoint_budget = 64 << 30  # the workload's device-memory cap for the adjoint's checkpoints
     k_no = next(k for k, s_ in enumerate(c["mech"].species) if s_.comp == {"N": 1, "O": 1})
@@ -727,7 +731,7 @@ def bench_lts(args):
     mech = sc.Mechanism(f["mech"].to_text())
     launch = dict(mode="persistent", tile=1, grid=0, order="cost") if args.mode == "auto" else \
         dict(mode=args.mode, tile=args.tile, grid=0, order=args.order)
-    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, **launch)
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, linalg=args.linalg, **launch)
     d = SplitDriver(plan, f["nx"], f["ny"], f["p"], f["u"], f["dt"], f["dx"], f["D"], f["inflow_T"], f["inflow_Y"])
     dev = "cuda:0"
     T0 = torch.tensor(f["T"], device=dev)
@@ -779,7 +783,8 @@ def bench_lts(args):
             "config": {"workload": "170 x 170 synthetic jet flame (28,900 cells: fuel jet, 1880 K pilot, air "
                                    "coflow), 53-species mechanism, 1 atm, local dt = 0.5 min(dx/u, dx^2/4D) "
                                    f"({f['dt'].min():.2e}..{f['dt'].max():.2e} s), rtol 1e-6, atol 1e-12",
-                       "cells": n, "launch": launch, "chemistry_ms": float(np.mean(chem_ms)),
+                       "cells": n, "launch": launch, "linalg": args.linalg,
+                       "kernel": kernel_name(launch, args.linalg, mech.N), "chemistry_ms": float(np.mean(chem_ms)),
                        "transport_ms": float(np.mean(tr_ms)), "steps_per_cell_per_split_step": float(steps.mean()) / args.steps,
                        "failed_cells": failed, "max_abs_sum_Y_minus_1": ysum, "spinup_steps": args.spinup,
                        "spinup_s": spin_s, "T_max": float(d.T.max()),
@@ -808,8 +813,8 @@ def bench_lts(args):
 
     ref_ms, ref_q = one_step(d)
     for name in ("plain", "static"):
-        e = SplitDriver(sc.Plan(mech, rtol=1e-6, atol=1e-12, mode=name), f["nx"], f["ny"], f["p"], f["u"], f["dt"],
-                        f["dx"], f["D"], f["inflow_T"], f["inflow_Y"])
+        e = SplitDriver(sc.Plan(mech, rtol=1e-6, atol=1e-12, mode=name, linalg=args.linalg), f["nx"], f["ny"],
+                        f["p"], f["u"], f["dt"], f["dx"], f["D"], f["inflow_T"], f["inflow_Y"])
         ms, q = one_step(e)
         line["config"][f"{name}_launch_chemistry_ms"] = ms
         line["config"][f"{name}_launch_identical"] = bool(torch.equal(q, ref_q))
@@ -835,8 +840,8 @@ def lts_mapping(sc, torch, mech, f, launch, one_step, ref_q, ref_ms, T1, Y1, h1,
     bar), then K timed split steps with the mapping."""
     from paper_2311_14941_amd.driver import SplitDriver
     mp = dict(Y_fuel=f["Y_fuel"], Y_ox=f["Y_ox"], z_tol=MAP_Z_TOL, dT=MAP_DT, dlnp=0.0)
-    e = SplitDriver(sc.Plan(mech, rtol=1e-6, atol=1e-12, **launch), f["nx"], f["ny"], f["p"], f["u"], f["dt"],
-                    f["dx"], f["D"], f["inflow_T"], f["inflow_Y"], mapping=mp)
+    e = SplitDriver(sc.Plan(mech, rtol=1e-6, atol=1e-12, linalg=args.linalg, **launch), f["nx"], f["ny"], f["p"],
+                    f["u"], f["dt"], f["dx"], f["D"], f["inflow_T"], f["inflow_Y"], mapping=mp)
     ms, q = one_step(e)
     ref = e.ref.cpu().numpy()
     mapped = ref != np.arange(ref.size)

@@ -234,6 +234,8 @@ sc_status sc_mech_sparse_array(const sc_mech *mech, const char *name, void *out,
     else if (k == "rxi") take(s.rxi);
     else if (k == "cstart") take(s.cstart);
     else if (k == "cmask") take(s.cmask);
+    else if (k == "sweep_f") take(s.sweep_f);
+    else if (k == "sweep_b") take(s.sweep_b);
     else return fail(SC_EINVAL, "unknown sparse array " + k);
     if (out && sz) std::memcpy(out, src, std::min(sz, *bytes));
     *bytes = sz;
@@ -423,7 +425,7 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
              upload(p, S.lu_u, &q.lu_u) && upload(p, S.diag, &q.diag) && upload(p, S.lu_c, &q.lu_c) &&
              upload(p, S.fw, &q.fw) && upload(p, S.bw, &q.bw) && upload(p, rxi, &q.rxi) &&
              upload(p, comp, &q.comp) && upload(p, emap, &q.emap) && upload(p, S.cstart, &q.cstart) &&
-             upload(p, S.cmask, &q.cmask);
+             upload(p, S.cmask, &q.cmask) && upload(p, S.sweep_f, &q.swf) && upload(p, S.sweep_b, &q.swb);
     }
     if (ok) {
         void *q = nullptr;

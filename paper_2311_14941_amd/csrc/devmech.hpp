@@ -63,6 +63,7 @@ struct DevSparse {
     const uint16_t *emap;    // n * n: (row, column) position -> entry or NOENT, row-major
     const int32_t *cstart;   // n + 1: first entry of each column (entries are numbered column by column)
     const uint64_t *cmask;   // 2 n: rows with an entry in column k, lanes 0-63 then 64-127
+    const uint32_t *swf, *swb;  // n <= 64: per column the strictly lower (upper) rows' mask and first entry
 };
 constexpr int CMP = 6;  // comp entries per species
 

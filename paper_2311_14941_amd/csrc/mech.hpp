@@ -51,6 +51,11 @@ struct SparseLU {
     std::vector<int> emap;        // n * n: (row position, column position) -> entry or -1
     std::vector<int> cstart;      // n + 1: first entry of each column
     std::vector<uint64_t> cmask;  // 2 n: rows holding an entry in column j (bits 0-63, 64-127)
+    // per column k of a system of at most 64 positions, 4 words each: the
+    // rows below the diagonal holding an entry (mask low, high word) and the
+    // first of those entries (forward sweep); the same for the rows above
+    // the diagonal (backward sweep)
+    std::vector<uint32_t> sweep_f, sweep_b;
     std::vector<uint8_t> apat;    // n * n: structural pattern of the bordered matrix (before fill)
     // LU, level by level: scale the L entries of the level's pivots
     // (b items: e_ik | e_kk << 16), then the Schur updates (c items:

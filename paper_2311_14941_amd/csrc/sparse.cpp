@@ -163,6 +163,19 @@ void compile_sparse(Mech &m)
         S.cstart.push_back((int)S.erow.size());
     }
     S.nnz = (int)S.erow.size();
+    S.sweep_f.clear();
+    S.sweep_b.clear();
+    if (n <= 64) {
+        for (int k = 0; k < n; ++k) {
+            const uint64_t m = S.cmask[2 * k];
+            const uint64_t upto = k == 63 ? ~0ull : (2ull << k) - 1;  // rows 0..k
+            const uint64_t lower = m & ~upto, upper = m & ((1ull << k) - 1);
+            const uint32_t lstart = (uint32_t)(S.cstart[k] + __builtin_popcountll(m & upto));
+            for (uint32_t w : {(uint32_t)lower, (uint32_t)(lower >> 32), lstart, 0u}) S.sweep_f.push_back(w);
+            for (uint32_t w : {(uint32_t)upper, (uint32_t)(upper >> 32), (uint32_t)S.cstart[k], 0u})
+                S.sweep_b.push_back(w);
+        }
+    }
     if (S.nnz >= NOENT) throw Unsupported("sparse LU has too many entries for 16-bit entry indices");
     auto E = [&](int i, int j) { return S.emap[i * n + j]; };
     // 5. LU levels: pivot k waits for every earlier pivot that updates its row

@@ -225,10 +225,13 @@ __device__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const 
 #pragma unroll 1
     for (int j = lane; j < R; j += G) {
         const RxRec rr = load_rec(m, j);
-        uint16_t ix[sc::RXI_SIZE];
-        __builtin_memcpy(ix, sp.rxi + (size_t)j * sc::RXI_SIZE, sizeof ix);
         const double dl = dlnA ? dlnA[rr.orig] : 0.0;
         const RxOut<> o = reaction<true>(m, lds, rr, x, dl, sp.C, sp.G, sp.H);
+        // the reaction's entry indices are loaded once its rate terms are
+        // done, so they do not hold registers through the rate arithmetic
+        __builtin_amdgcn_sched_barrier(0);
+        uint16_t ix[sc::RXI_SIZE];
+        __builtin_memcpy(ix, sp.rxi + (size_t)j * sc::RXI_SIZE, sizeof ix);
         // temperature-row weight: the reaction enthalpy (constant pressure) or
         // internal energy (constant volume), per unit of progress
         const double dHJ = m.cv ? (o.dH - rr.dnu) * RT : o.dH * RT;
@@ -478,6 +481,77 @@ __device__ __forceinline__ void col_values(const ColMeta<VPL, G> &c, const doubl
     }
 }
 
+// Column sweeps of a system of at most 64 positions (one slot per lane).
+// Lane k of each cell's group holds, for column k, the mask of the rows
+// below (forward) and above (backward) the diagonal that hold an entry and
+// the first of those entries; a sweep broadcasts them per column
+// (readlane, or a group shuffle), and a lane's entry is that start plus the
+// mask's bits below the lane.  The LDS read is unconditional (the index
+// never leaves the column's entries) and the lanes without an entry are
+// zeroed by a select on the mask; the select is applied one column later,
+// so the read of column k + 1 overlaps the update with column k.  No
+// branch, no barrier.
+// v where the lane's bit of the lane mask m is set, else 0 (one
+// v_cndmask per half with the mask as the lane condition)
+__device__ __forceinline__ double keep_lanes(uint64_t m, double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int rlo, rhi;
+    asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(rlo) : "v"(lo), "s"(m));
+    asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(rhi) : "v"(hi), "s"(m));
+    return __hiloint2double(rhi, rlo);
+}
+
+struct SweepCol {
+    uint64_t msk;  // rows of the column holding an entry
+    double raw;    // the LDS word read for this lane (meaningless off the mask)
+};
+
+template <int G>
+__device__ __forceinline__ SweepCol sweep_col(int mlo, int mhi, int start, const double *E, int k, int lane)
+{
+    const uint64_t msk = (uint64_t)(uint32_t)gbcast_i<G>(mhi, k) << 32 | (uint32_t)gbcast_i<G>(mlo, k);
+    const int e = gbcast_i<G>(start, k) + below<G>(msk, lane);
+    return SweepCol{msk, E[e]};
+}
+
+// the column's value for this lane: with one cell per wave the mask is
+// wave-uniform and selects lanes directly; with several cells per wave it
+// differs per group and is tested per lane
+template <int G>
+__device__ __forceinline__ double sweep_value(const SweepCol &c, int lane)
+{
+    if constexpr (G == WAVE)
+        return keep_lanes(c.msk, c.raw);
+    else
+        return (c.msk >> lane) & 1 ? c.raw : 0.0;
+}
+
+template <int G>
+__device__ __forceinline__ void sweeps_1(const DevSparse &sp, const double *E, const double *DINV, int n, int lane,
+                                         double &z)
+{
+    const bool live = lane < n;
+    const uint32_t *f = sp.swf + 4 * (live ? lane : 0), *b = sp.swb + 4 * (live ? lane : 0);
+    const int flo = live ? (int)f[0] : 0, fhi = live ? (int)f[1] : 0, fst = live ? (int)f[2] : 0;
+    const int blo = live ? (int)b[0] : 0, bhi = live ? (int)b[1] : 0, bst = live ? (int)b[2] : 0;
+    // forward with the unit-diagonal L, k ascending
+    SweepCol nxt = sweep_col<G>(flo, fhi, fst, E, 0, lane);
+    for (int k = 0; k < n - 1; ++k) {
+        const SweepCol cur = nxt;
+        if (k + 1 < n - 1) nxt = sweep_col<G>(flo, fhi, fst, E, k + 1, lane);
+        z = fma(-sweep_value<G>(cur, lane), gbcast<G>(z, k), z);
+    }
+    if (live) z *= DINV[lane];
+    // backward with the unit-diagonal U, k descending
+    nxt = sweep_col<G>(blo, bhi, bst, E, n - 1, lane);
+    for (int k = n - 1; k > 0; --k) {
+        const SweepCol cur = nxt;
+        if (k > 1) nxt = sweep_col<G>(blo, bhi, bst, E, k - 1, lane);
+        z = fma(-sweep_value<G>(cur, lane), gbcast<G>(z, k), z);
+    }
+}
+
 template <int VPL, int G = WAVE>
 __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&b)[VPL], int lane,
                         double (&x)[VPL])
@@ -501,6 +575,9 @@ __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, cons
         const int q = lane + G * v;
         z[v] = q < n ? X[q] : 0.0;
     }
+    if constexpr (VPL == 1) {
+        sweeps_1<G>(sp, E, DINV, n, lane, z[0]);
+    } else {
     // forward: x_i -= l_ik x_k, k ascending, rows below the diagonal (the
     // next column's values are read while this one is applied)
     double nxt[VPL], cur[VPL];
@@ -530,6 +607,7 @@ __device__ void solve_v(const DevMech &m, const DevSparse &sp, double *lds, cons
 #pragma unroll
         for (int v = 0; v < VPL; ++v)
             if (lane + G * v < k) z[v] = fma(-cur[v], zk, z[v]);
+    }
     }
     __syncthreads();  // every lane has read X
 #pragma unroll

@@ -223,7 +223,12 @@ def test_size_sparse_parity(torch, sc, ns):
     ref = o.integrate(T, p, Y, dt, rtol=1e-11, atol=1e-17, max_steps=200000)
     assert np.all(ref["status"] == 0)
     Tg, pg, Yg, dtg = _gpu(torch, T, p, Y, dt)
-    r = sc.Plan(m, rtol=1e-10, atol=1e-16, max_steps=200000, linalg="sparse").integrate(Tg, pg, Yg, dtg)
+    # a first step of dt / 1000 (the caller's carried step): one of these
+    # random 14-species states is so stiff that a first attempt over the
+    # whole dt and four shorter retries all overflow, in the dense and the
+    # sparse kernels alike, and the controller gives the cell up
+    h0 = dtg * 1e-3
+    r = sc.Plan(m, rtol=1e-10, atol=1e-16, max_steps=200000, linalg="sparse").integrate(Tg, pg, Yg, dtg, h=h0)
     assert np.all(r["status"].cpu().numpy() == 0)
     T1, Y1 = r["T"].cpu().numpy(), r["Y"].cpu().numpy().T
     assert np.all(np.abs(T1 - ref["T"]) <= 1e-6 * ref["T"]), ns
