@@ -165,7 +165,10 @@ def main():
     else:
         launch = dict(mode=args.mode, tile=args.tile, grid=0, order=args.order)
         tune_ms = None
-    cpw = launch.pop("cells_per_wave", args.cells_per_wave) if args.linalg == "sparse" else 0
+    # cells per wave is a sparse-family setting (the dense kernels take one cell per wave)
+    cpw = launch.pop("cells_per_wave", args.cells_per_wave)
+    if args.linalg != "sparse":
+        cpw = 0
     plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, method=args.method, linalg=args.linalg,
                    cells_per_wave=cpw, **launch)
     use_pred = launch["mode"] == "persistent" and launch["order"] == "cost"

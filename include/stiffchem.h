@@ -161,6 +161,9 @@ typedef struct {
     int64_t flops_lu_sparse;    /* one factorisation (division 1, fma 2) */
     int64_t flops_solve_sparse; /* one solve */
     int64_t flops_step_sparse;  /* one step with the sparse linear algebra */
+    int32_t lu_tail_sparse;     /* trailing positions whose L+U block is full: factorised in
+                                 * registers after the level schedule (its pivots are not in
+                                 * lu_levels; flops_lu_sparse counts them) */
 } sc_mech_info;
 
 void sc_default_options(sc_options *opt);
@@ -186,13 +189,19 @@ sc_status sc_species_index(const sc_mech *mech, const char *name, int32_t *idx);
  *     entries are numbered column by column, rows ascending),
  *   "cstart" (int32, n + 1: first entry of each column), "cmask" (uint64,
  *     2 per column: bit i of word i / 64 set when row i has an entry),
+ *   "sweep_f", "sweep_b" (uint32, n <= 64 only, 4 per column: mask of the
+ *     rows below (above) the diagonal holding an entry, low and high word,
+ *     and the first of those entries, then 0),
  *   "lu_b_lvl", "lu_c_lvl", "fw_lvl", "bw_lvl", "tfw_lvl", "tbw_lvl" (int32
  *     level offsets), "lu_b", "lu_u", "diag" (uint32 items), "lu_c", "fw",
  *     "bw", "tfw", "tbw" (uint64 items), "rxi" (uint16, RXI entries per
  *     reaction in mechanism order).
  * Item encodings: lu_b e_ik | e_kk << 16 (l_ik = a_ik / a_kk); lu_c
  * e_ij | e_ik << 16 | e_kj << 32 (a_ij -= l_ik u_kj); lu_u e_kj | k << 16
- * (u_kj /= u_kk); solves i | p << 16 | e << 32 (x_i -= a_e x_p).
+ * (u_kj /= u_kk); solves i | p << 16 | e << 32 (x_i -= a_e x_p).  lu_b and
+ * lu_c hold the pivots before the dense tail only (sc_mech_info's
+ * lu_tail_sparse): the last lu_tail_sparse pivots are eliminated densely
+ * after the levels, with the same operations.
  * SC_EINVAL for an unknown name. */
 sc_status sc_mech_sparse_array(const sc_mech *mech, const char *name, void *out, size_t *bytes);
 void sc_mech_free(sc_mech *mech);

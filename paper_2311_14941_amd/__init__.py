@@ -55,7 +55,8 @@ class MechInfo(C.Structure):
                                          "flops_step")] + \
                [(n, C.c_int32) for n in ("nnz_a_sparse", "nnz_lu_sparse", "lu_levels", "solve_levels")] + \
                [(n, C.c_int64) for n in ("lu_updates_sparse", "flops_lu_sparse", "flops_solve_sparse",
-                                         "flops_step_sparse")]
+                                         "flops_step_sparse")] + \
+               [("lu_tail_sparse", C.c_int32)]
 
 
 _lib = None
@@ -143,7 +144,8 @@ class Mechanism:
                       "lu_b_lvl": "int32", "lu_c_lvl": "int32", "fw_lvl": "int32", "bw_lvl": "int32",
                       "tfw_lvl": "int32", "tbw_lvl": "int32", "lu_b": "uint32", "lu_u": "uint32",
                       "diag": "uint32", "lu_c": "uint64", "fw": "uint64", "bw": "uint64", "tfw": "uint64",
-                      "tbw": "uint64", "rxi": "uint16"}
+                      "tbw": "uint64", "rxi": "uint16", "cstart": "int32", "cmask": "uint64",
+                      "sweep_f": "uint32", "sweep_b": "uint32"}
 
     def sparse_array(self, name: str):
         """One array of the compiled sparse algebra (sc_mech_sparse_array) as

@@ -198,6 +198,7 @@ sc_status sc_mech_info_get(const sc_mech *mech, sc_mech_info *out)
     out->flops_lu_sparse = m.cnt_sparse.flops_lu;
     out->flops_solve_sparse = m.cnt_sparse.flops_solve;
     out->flops_step_sparse = m.cnt_sparse.flops_step;
+    out->lu_tail_sparse = m.sp.n - m.sp.tail0;
     return SC_OK;
 }
 
@@ -305,6 +306,7 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
         ds.nl_fw = (int)S.fw_lvl.size() - 1;
         ds.nl_bw = (int)S.bw_lvl.size() - 1;
         ds.n_u = (int)S.lu_u.size();
+        ds.tail0 = S.tail0;
         ds.NV = NV;
         ds.E = 0;
         ds.C = S.nnz;
@@ -318,6 +320,9 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
         ds.size = ds.DINV + S.n;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(SC_EHIP, "hipGetDeviceProperties failed");
+        // the register tail: at most SPARSE_TAIL_MAX rows, and no more than a cell's lanes
+        if (S.n - S.tail0 > std::min(sc::SPARSE_TAIL_MAX, 64 / cpw))
+            return fail(SC_EUNSUPPORTED, "dense LU tail wider than a cell's lanes");
         if (sizeof(double) * (size_t)ds.size * cpw > prop.sharedMemPerBlock)
             return fail(SC_EUNSUPPORTED, "the sparse factors of this mechanism need " +
                                              std::to_string(sizeof(double) * ds.size) +

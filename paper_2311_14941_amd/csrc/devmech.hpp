@@ -54,6 +54,7 @@ struct DevSparse {
     int E, C, G, H, WD, UA, U, X, DINV, size;  // LDS offsets of one cell's region and its size (doubles)
     int NV;   // vector stride: lanes per cell times slots per lane
     int cpw;  // cells per wave (1, 2 or 4): each cell takes 64 / cpw lanes
+    int tail0;  // first position of the dense trailing block (factorised in registers)
     const int *lu_b_lvl, *lu_c_lvl, *fw_lvl, *bw_lvl;
     const uint64_t *lu_b;  // widened to the c items' width: e_ik | e_kk << 16
     const uint32_t *lu_u, *diag;

@@ -178,19 +178,34 @@ void compile_sparse(Mech &m)
     }
     if (S.nnz >= NOENT) throw Unsupported("sparse LU has too many entries for 16-bit entry indices");
     auto E = [&](int i, int j) { return S.emap[i * n + j]; };
-    // 5. LU levels: pivot k waits for every earlier pivot that updates its row
-    //    or column (k in L_p or in U_p)
+    // 5. the dense trailing block: the widest [t, n) of at most
+    //    SPARSE_TAIL_MAX positions whose L+U pattern is full (the trailing
+    //    Schur complement of a minimum-degree order fills in).  Its pivots
+    //    would take one level each; they are factorised in registers instead,
+    //    after the levels of the pivots before t.
+    S.tail0 = n;
+    while (S.tail0 > 0 && n - S.tail0 < SPARSE_TAIL_MAX) {
+        const int q = S.tail0 - 1;
+        bool full = true;
+        for (int i = q; i < n && full; ++i) full = F[(size_t)i * n + q] && F[(size_t)q * n + i];
+        if (!full) break;
+        S.tail0 = q;
+    }
+    // 6. LU levels of the pivots before the tail: pivot k waits for every
+    //    earlier pivot that updates its row or column (k in L_p or in U_p);
+    //    at least one (possibly empty) level
     std::vector<int> lev(n, 0);
     for (int p = 0; p < n; ++p) {
         for (int i : Lc[p]) lev[i] = std::max(lev[i], lev[p] + 1);
         for (int j : Ur[p]) lev[j] = std::max(lev[j], lev[p] + 1);
     }
-    const int nl = *std::max_element(lev.begin(), lev.end()) + 1;
+    int nl = 1;
+    for (int k = 0; k < S.tail0; ++k) nl = std::max(nl, lev[k] + 1);
     S.lu_b_lvl.assign(1, 0);
     S.lu_c_lvl.assign(1, 0);
     int64_t nL = 0, nU = 0;
     for (int l = 0; l < nl; ++l) {
-        for (int k = 0; k < n; ++k) {
+        for (int k = 0; k < S.tail0; ++k) {
             if (lev[k] != l) continue;
             for (int i : Lc[k]) S.lu_b.push_back((uint32_t)E(i, k) | (uint32_t)E(k, k) << 16);
             for (int i : Lc[k])
@@ -208,7 +223,7 @@ void compile_sparse(Mech &m)
         S.updates += (int64_t)Lc[k].size() * (int64_t)Ur[k].size();
         for (int j : Ur[k]) S.lu_u.push_back((uint32_t)E(k, j) | (uint32_t)k << 16);
     }
-    // 6. solves.  Forward (unit L): x_i -= l_ip x_p.  Backward (U scaled to a
+    // 7. solves.  Forward (unit L): x_i -= l_ip x_p.  Backward (U scaled to a
     //    unit diagonal, after x *= 1/u_kk): x_k -= u'_kj x_j.
     std::vector<std::vector<int>> rd(n);
     std::vector<std::array<int, 3>> items;
@@ -235,7 +250,7 @@ void compile_sparse(Mech &m)
     for (int p = 0; p < n; ++p)
         for (int i : Lc[p]) rd[p].push_back(i), items.push_back({p, i, E(i, p)});
     group_by_source(items, solve_levels(rd, down), S.tbw_lvl, S.tbw);
-    // 7. the entries each reaction's derivative terms are scattered into
+    // 8. the entries each reaction's derivative terms are scattered into
     S.rxi.assign((size_t)R * RXI_SIZE, NOENT);
     for (int j = 0; j < R; ++j) {
         const Reaction &r = m.rx[j];
@@ -272,7 +287,7 @@ void compile_sparse(Mech &m)
     S.e_SS = E(pS, pS);
     S.e_TS = E(pT, pS);
     S.e_ST = E(pS, pT);
-    // 8. work of the schedule (fma = 2 flops, division = 1): LU = one division
+    // 9. work of the schedule (fma = 2 flops, division = 1): LU = one division
     //    per L entry, one fma per Schur update, the reciprocal of every pivot
     //    and the row scaling of U; a solve = the scaled right-hand side (1/W_k
     //    per species), one fma per L and U entry, the pivot scaling, and the

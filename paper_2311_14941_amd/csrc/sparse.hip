@@ -366,8 +366,54 @@ __device__ __forceinline__ void lu_update_items(double *E, const uint64_t (&it)[
         if (it[u] != ~0ull) atomicAdd(&E[lo16(it[u])], -a[u] * b[u]);
 }
 
-// Numeric LU of the formed matrix in E by the static level schedule, then
-// dinv = 1/u_kk and the rows of U scaled to a unit diagonal.
+// The dense trailing block [t0, n) (w = n - t0 <= W positions, full L+U
+// pattern) in registers: lane r holds row t0 + r, columns t0..n-1.  The
+// rows of the block are the last w entries of each of its columns (entries
+// are numbered column by column), so no index table is read.  Right-looking
+// elimination: per pivot k, the pivot row is broadcast entry by entry and
+// every row below applies it; rows at or above the pivot multiply by zero.
+// Padding (rows and columns from w to W) holds zeros and takes part
+// unconditionally: the loops have fixed trip counts, the array stays in
+// registers.  L is stored scaled (l_ik = a_ik / a_kk), U and the diagonal
+// as computed.  The same operations as the level schedule would perform,
+// without its barriers and schedule loads (one level per pivot in a dense
+// block).
+template <int G, int W>
+__device__ __forceinline__ void lu_tail(const DevSparse &sp, double *E, int lane)
+{
+    const int n = sp.n, t0 = sp.tail0, w = n - t0;
+    const bool row = lane < w;
+    const int back = n - t0 - lane;  // entry (t0 + lane, c) = cstart[c + 1] - back
+    const int cend = row ? sp.cstart[t0 + lane + 1] : 0;  // lane j: end of column t0 + j
+    double a[W];
+    // loads at a clamped index and selects (no lane mask per column is kept
+    // alive until the stores)
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const int e = gbcast_i<G>(cend, j) - back;
+        const bool ok = j < w && row;
+        const double x = E[ok ? e : 0];
+        a[j] = ok ? x : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < W - 1; ++k) {
+        const double akk = gbcast<G>(a[k], k);
+        const bool sub = row && lane > k;  // a row below the pivot
+        const double l = sub ? a[k] / akk : 0.0;
+        a[k] = sub ? l : a[k];
+#pragma unroll
+        for (int j = k + 1; j < W; ++j) a[j] = fma(-l, gbcast<G>(a[j], k), a[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const int e = gbcast_i<G>(cend, j) - back;
+        if (j < w && row) E[e] = a[j];
+    }
+}
+
+// Numeric LU of the formed matrix in E: the static level schedule of the
+// pivots before the dense tail, the tail in registers, then dinv = 1/u_kk
+// and the rows of U scaled to a unit diagonal.
 template <int G>
 __device__ void lu_v(const DevSparse &sp, double *lds, int lane)
 {
@@ -395,6 +441,8 @@ __device__ void lu_v(const DevSparse &sp, double *lds, int lane)
             __syncthreads();
         }
     }
+    lu_tail<G, (G < sc::SPARSE_TAIL_MAX ? G : sc::SPARSE_TAIL_MAX)>(sp, E, lane);
+    __syncthreads();
 #pragma unroll 1
     for (int k = lane; k < sp.n; k += G) DINV[k] = 1.0 / E[sp.diag[k]];
     __syncthreads();

@@ -348,15 +348,16 @@ def test_launch_modes_bitwise_equal(torch, sc):
         assert torch.equal(ref[k], out[k]), ("cost", k)
 
 
-def test_chained_substeps_graph_replay(torch, sc):
+@pytest.mark.parametrize("linalg", ["dense", "sparse"])
+def test_chained_substeps_graph_replay(torch, sc, linalg):
     """Chained substeps captured in a HIP graph: every replay (with eager work
-    in between) equals the eager chain."""
+    in between) equals the eager chain, for both linear-algebra families."""
     c = cells("C2")
     mech = sc.Mechanism(c["mech"].to_text())
     idx = np.arange(0, 65536, 256)
     T, p, Y, dt = to_gpu(torch, c, idx)
     for mode in ("plain", "persistent"):
-        plan = sc.Plan(mech, mode=mode)
+        plan = sc.Plan(mech, mode=mode, linalg=linalg)
         eager = sc.Chain(plan, T, p, Y, dt / 4, nsub=4, graph=False)
         Te, Ye, he, se = [x.clone() for x in eager.run(T, Y)]
         g = sc.Chain(plan, T, p, Y, dt / 4, nsub=4, graph=True)

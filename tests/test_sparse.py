@@ -54,8 +54,8 @@ class Replay:
     (repeated targets accumulate, as the device's LDS atomics do), items in
     a shuffled order.  Counts the floating-point work it performs."""
 
-    def __init__(self, a, rng):
-        self.a, self.rng, self.flops = a, rng, 0
+    def __init__(self, a, rng, tail):
+        self.a, self.rng, self.flops, self.tail = a, rng, 0, tail
 
     def _shuf(self, x):
         return x[self.rng.permutation(x.size)]
@@ -69,6 +69,19 @@ class Replay:
             c = self._shuf(a["lu_c"][a["lu_c_lvl"][l]:a["lu_c_lvl"][l + 1]])
             np.subtract.at(v, lo(c), v[mid(c)] * v[hi(c)])
             self.flops += 2 * c.size
+        # the dense trailing block, eliminated pivot by pivot after the levels
+        n = a["perm"].size
+        emap = -np.ones((n, n), dtype=np.int64)
+        emap[a["erow"], a["ecol"]] = np.arange(a["erow"].size)
+        t0 = n - self.tail
+        assert np.all(emap[t0:, t0:] >= 0), "the tail block must be full"
+        for k in range(t0, n):
+            rows = emap[k + 1:, k]
+            v[rows] = v[rows] / v[emap[k, k]]
+            self.flops += rows.size
+            blk = emap[k + 1:, k + 1:]
+            v[blk] -= np.outer(v[rows], v[emap[k, k + 1:]])
+            self.flops += 2 * blk.size
         d = a["diag"].astype(np.int64)
         dinv = 1.0 / v[d]
         self.flops += d.size
@@ -115,13 +128,33 @@ def test_schedule_solves_like_numpy(key):
         A = np.where(P, rng.normal(size=(n, n)), 0.0)
         A[np.arange(n), np.arange(n)] = n + rng.uniform(1, 2, n)
         v = A[er, ec].copy()  # fill entries start at zero
-        r = Replay(a, rng)
+        r = Replay(a, rng, cm.info["lu_tail_sparse"])
         dinv = r.lu(v)
         b = rng.normal(size=n)
         x = r.solve(v, dinv, b.copy())
         assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-12, atol=1e-12 * np.abs(x).max())
         w = r.solve_t(v, dinv, b.copy())
         assert np.allclose(w, np.linalg.solve(A.T, b), rtol=1e-12, atol=1e-12 * np.abs(w).max())
+
+
+@pytest.mark.parametrize("key,width", [("h2_9", 9), ("chon_53", 30), ("chon_110", 32)])
+def test_dense_tail_is_the_widest_full_block(key, width):
+    """The register-factorised tail is the widest trailing block of the
+    filled L+U pattern that is full, capped at 32 positions, and the level
+    schedule holds exactly the pivots before it."""
+    _, cm = mech(key)
+    a = arrays(cm)
+    n = a["perm"].size
+    w = cm.info["lu_tail_sparse"]
+    assert w == width
+    F = np.zeros((n, n), dtype=bool)
+    F[a["erow"], a["ecol"]] = True
+    t0 = n - w
+    assert F[t0:, t0:].all()
+    assert w == 32 or t0 == 0 or not F[t0 - 1:, t0 - 1:].all()
+    # b items: the L entries of the scheduled pivots (columns before t0)
+    piv = a["ecol"][lo(a["lu_b"].astype(np.uint64))]
+    assert np.all(piv < t0) and a["lu_b"].size == int(np.sum((a["erow"] > a["ecol"]) & (a["ecol"] < t0)))
 
 
 @pytest.mark.parametrize("key", ["h2_9", "chon_53", "chon_110"])
@@ -135,13 +168,14 @@ def test_schedule_work_equals_counted_replay(key):
     rng = np.random.default_rng(5)
     A = np.where(a["apat"].reshape(n, n).astype(bool), rng.normal(size=(n, n)), 0.0) + n * np.eye(n)
     v = A[a["erow"], a["ecol"]].copy()
-    r = Replay(a, rng)
+    r = Replay(a, rng, cm.info["lu_tail_sparse"])
     dinv = r.lu(v)
     assert r.flops == cm.info["flops_lu_sparse"]
     r.flops = 0
     r.solve(v, dinv, rng.normal(size=n))
     assert r.flops + 2 * m.n_species == cm.info["flops_solve_sparse"]
-    assert cm.info["lu_updates_sparse"] == a["lu_c"].size
+    w = cm.info["lu_tail_sparse"]
+    assert cm.info["lu_updates_sparse"] == a["lu_c"].size + sum(q * q for q in range(w))
     assert cm.info["nnz_lu_sparse"] == a["erow"].size
     # the ordering is a permutation with the borders (T, sigma) last
     assert sorted(a["perm"]) == list(range(n)) and list(a["perm"][-2:]) == [n - 2, n - 1]
