@@ -320,8 +320,8 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
         ds.size = ds.DINV + S.n;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(SC_EHIP, "hipGetDeviceProperties failed");
-        // the register tail: at most SPARSE_TAIL_MAX rows, and no more than a cell's lanes
-        if (S.n - S.tail0 > std::min(sc::SPARSE_TAIL_MAX, 64 / cpw))
+        // the register tail: at most sparse_tail_max(n) rows, and no more than a cell's lanes
+        if (S.n - S.tail0 > std::min(sc::sparse_tail_max(S.n), 64 / cpw))
             return fail(SC_EUNSUPPORTED, "dense LU tail wider than a cell's lanes");
         if (sizeof(double) * (size_t)ds.size * cpw > prop.sharedMemPerBlock)
             return fail(SC_EUNSUPPORTED, "the sparse factors of this mechanism need " +

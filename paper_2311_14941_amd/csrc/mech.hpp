@@ -21,7 +21,12 @@ constexpr int MAXENH = 4;                   // enhanced third-body species per r
 constexpr int NDEP = 2 * MAXSIDE + MAXENH;  // dependency slots per reaction
 constexpr int MAX_STATE = 64;               // N + 1 supported by the dense one-wave kernels
 constexpr int MAX_STATE_SPARSE = 128;       // N + 1 supported by the sparse kernels (two components per lane)
-constexpr int SPARSE_TAIL_MAX = 32;         // widest dense trailing block of the sparse LU held in registers
+// widest dense trailing block of the sparse LU held in registers: systems
+// of up to 64 positions (two waves per SIMD, a tighter register budget),
+// and wider ones (one wave per SIMD)
+constexpr int SPARSE_TAIL_MAX = 32;
+constexpr int SPARSE_TAIL_MAX_WIDE = 64;
+constexpr int sparse_tail_max(int n) { return n <= 64 ? SPARSE_TAIL_MAX : SPARSE_TAIL_MAX_WIDE; }
 // per-reaction entry indices of the sparse kernels: for each row slot (3
 // reactants, 3 products) the entries of its dependency slots and of the
 // temperature column, then the temperature row's entries of the dependency
@@ -66,7 +71,7 @@ struct SparseLU {
     std::vector<uint64_t> lu_c;
     std::vector<uint32_t> lu_u;           // strict U entries with their pivot: e_kj | k << 16 (row scaling)
     // the dense trailing block [tail0, n) (full L+U pattern, at most
-    // SPARSE_TAIL_MAX positions): its pivots are not in the level schedule
+    // sparse_tail_max(n) positions): its pivots are not in the level schedule
     // but factorised in registers after it
     int tail0 = 0;
     std::vector<uint32_t> diag;           // diagonal entry of each position

@@ -179,12 +179,12 @@ void compile_sparse(Mech &m)
     if (S.nnz >= NOENT) throw Unsupported("sparse LU has too many entries for 16-bit entry indices");
     auto E = [&](int i, int j) { return S.emap[i * n + j]; };
     // 5. the dense trailing block: the widest [t, n) of at most
-    //    SPARSE_TAIL_MAX positions whose L+U pattern is full (the trailing
+    //    sparse_tail_max(n) positions whose L+U pattern is full (the trailing
     //    Schur complement of a minimum-degree order fills in).  Its pivots
     //    would take one level each; they are factorised in registers instead,
     //    after the levels of the pivots before t.
     S.tail0 = n;
-    while (S.tail0 > 0 && n - S.tail0 < SPARSE_TAIL_MAX) {
+    while (S.tail0 > 0 && n - S.tail0 < sparse_tail_max(n)) {
         const int q = S.tail0 - 1;
         bool full = true;
         for (int i = q; i < n && full; ++i) full = F[(size_t)i * n + q] && F[(size_t)q * n + i];

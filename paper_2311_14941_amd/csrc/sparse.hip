@@ -414,7 +414,7 @@ __device__ __forceinline__ void lu_tail(const DevSparse &sp, double *E, int lane
 // Numeric LU of the formed matrix in E: the static level schedule of the
 // pivots before the dense tail, the tail in registers, then dinv = 1/u_kk
 // and the rows of U scaled to a unit diagonal.
-template <int G>
+template <int VPL, int G>
 __device__ void lu_v(const DevSparse &sp, double *lds, int lane)
 {
     double *E = lds + sp.E;
@@ -441,7 +441,9 @@ __device__ void lu_v(const DevSparse &sp, double *lds, int lane)
             __syncthreads();
         }
     }
-    lu_tail<G, (G < sc::SPARSE_TAIL_MAX ? G : sc::SPARSE_TAIL_MAX)>(sp, E, lane);
+    // the tail width the kernel holds: one slot per lane (n <= 64) or two
+    constexpr int W = VPL == 1 ? (G < sc::SPARSE_TAIL_MAX ? G : sc::SPARSE_TAIL_MAX) : sc::SPARSE_TAIL_MAX_WIDE;
+    lu_tail<G, W>(sp, E, lane);
     __syncthreads();
 #pragma unroll 1
     for (int k = lane; k < sp.n; k += G) DINV[k] = 1.0 / E[sp.diag[k]];
@@ -685,7 +687,7 @@ __device__ void ros_attempt_v(const DevMech &m, const DevSparse &sp, const Opts 
     const int NV = sp.NV;
     double f0[VPL], flast[VPL];
     jac_v<VPL, G>(m, sp, lds, y, p, dlnA, lane, 1.0 / (GAM * hc), f0);
-    lu_v<G>(sp, lds, lane);
+    lu_v<VPL, G>(sp, lds, lane);
     const double ih = 1.0 / hc;
 #pragma unroll
     for (int v = 0; v < VPL; ++v) flast[v] = f0[v];
@@ -955,7 +957,7 @@ __global__ void __launch_bounds__(WAVE) k_linsolve_sp(DevMech mk, DevSparse sp, 
     double y[VPL], f[VPL], bb[VPL], xx[VPL];
     load_state_v<VPL, G>(m, T, Y, ld, c, lane, y);
     jac_v<VPL, G>(m, sp, ldsg, y, P[c], dlnA, lane, 1.0 / hg[c], f);
-    lu_v<G>(sp, ldsg, lane);
+    lu_v<VPL, G>(sp, ldsg, lane);
     const int nn = m.N + 1;
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {

@@ -137,11 +137,12 @@ def test_schedule_solves_like_numpy(key):
         assert np.allclose(w, np.linalg.solve(A.T, b), rtol=1e-12, atol=1e-12 * np.abs(w).max())
 
 
-@pytest.mark.parametrize("key,width", [("h2_9", 9), ("chon_53", 30), ("chon_110", 32)])
+@pytest.mark.parametrize("key,width", [("h2_9", 9), ("chon_53", 30), ("chon_110", 64)])
 def test_dense_tail_is_the_widest_full_block(key, width):
     """The register-factorised tail is the widest trailing block of the
-    filled L+U pattern that is full, capped at 32 positions, and the level
-    schedule holds exactly the pivots before it."""
+    filled L+U pattern that is full, capped at 32 positions for systems of
+    up to 64 positions and at 64 beyond, and the level schedule holds
+    exactly the pivots before it."""
     _, cm = mech(key)
     a = arrays(cm)
     n = a["perm"].size
@@ -151,7 +152,7 @@ def test_dense_tail_is_the_widest_full_block(key, width):
     F[a["erow"], a["ecol"]] = True
     t0 = n - w
     assert F[t0:, t0:].all()
-    assert w == 32 or t0 == 0 or not F[t0 - 1:, t0 - 1:].all()
+    assert w == (32 if n <= 64 else 64) or t0 == 0 or not F[t0 - 1:, t0 - 1:].all()
     # b items: the L entries of the scheduled pivots (columns before t0)
     piv = a["ecol"][lo(a["lu_b"].astype(np.uint64))]
     assert np.all(piv < t0) and a["lu_b"].size == int(np.sum((a["erow"] > a["ecol"]) & (a["ecol"] < t0)))
