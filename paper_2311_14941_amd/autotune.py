@@ -61,7 +61,7 @@ def tune(mech, T, p, Y, dt, device=0, rtol=1e-6, atol=1e-12, candidates=CANDIDAT
     # bits, different settings agree to rounding (checked against the
     # integrator's tolerance)
     npos = mech.N + 2
-    cpws = [1] if linalg != "sparse" else [c for c in (1, 2, 4) if npos <= 64 // c]
+    cpws = [1] if linalg != "sparse" else [c for c in (1, 2, 4) if c == 1 or npos <= 64 // c]
     ref_any = None
     for cpw in cpws:
         ref = None

@@ -378,3 +378,16 @@ def test_autotuner_picks_a_valid_config(torch, sc):
     args = to_gpu(torch, c, np.arange(2048))
     best, times = autotune.tune(mech, *args, use_cache=False, reps=1)
     assert best["mode"] in ("plain", "static", "persistent") and len(times) == len(autotune.CANDIDATES)
+
+
+def test_autotuner_sparse_wide_mechanism(torch, sc):
+    """The sparse family on the 110-species mechanism (two positions per
+    lane): one cell per wave is the only setting, and the tuner still picks
+    among the launches."""
+    from paper_2311_14941_amd import autotune
+    from synth.cells import make_cells
+    c = make_cells("C3", n=512)
+    mech = sc.Mechanism(c["mech"].to_text())
+    args = to_gpu(torch, c, np.arange(512))
+    best, times = autotune.tune(mech, *args, use_cache=False, reps=1, linalg="sparse")
+    assert best["cells_per_wave"] == 1 and len(times) == len(autotune.CANDIDATES)
