@@ -525,7 +525,11 @@ def bench_chained(args):
         # with the gradient: the forward and the adjoint's recording pass run
         # the same (dense) kernels, so the recorded trajectory is the forward's
         args.linalg = "dense"
-    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, linalg=args.linalg)
+    # launch: the persistent queue in index order unless --mode says otherwise
+    # (the captured graph replays the same launches; a cost order would need
+    # the previous substep's counts sorted inside the graph)
+    mode = "persistent" if args.mode == "auto" else args.mode
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, linalg=args.linalg, mode=mode)
     plan.adjoint_budget = 64 << 30  # the workload's device-memory cap for the adjoint's checkpoints
     k_no = next(k for k, s_ in enumerate(c["mech"].species) if s_.comp == {"N": 1, "O": 1})
     log("bench: capture + forward")
@@ -542,7 +546,7 @@ def bench_chained(args):
                 "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
                 "config": {"workload": f"{key}: 65,536 cells, {mech.N}-species mechanism, C2 classes, 20 chained "
                                        "substeps of 5e-5 s (state and step size carried), rtol 1e-6",
-                           "substeps": nsub, "linalg": args.linalg,
+                           "substeps": nsub, "linalg": args.linalg, "mode": mode,
                            "gradient": "not run: the adjoint supports up to 63 species (dense family)"},
                 "forward_graph_ms": fwd_ms, "cells_per_s": T.numel() * nsub / (fwd_ms / 1e3),
                 "steps_per_cell_mean": float(steps.double().mean().item()),
@@ -573,7 +577,8 @@ def bench_chained(args):
             "data": "synthetic",
             "config": {"workload": f"{key}: 65,536 cells, {mech.N}-species mechanism, C2 classes, 20 chained "
                                    "substeps of 5e-5 s (state and step size carried), rtol 1e-6, adjoint "
-                                   "workspace capped at 64 GB", "substeps": nsub, "linalg": args.linalg},
+                                   "workspace capped at 64 GB", "substeps": nsub, "linalg": args.linalg,
+                       "mode": mode},
             "forward_graph_ms": fwd_ms, "autograd_forward_ms": (t1 - t0) * 1e3,
             "backward_ms": (t2 - t1) * 1e3, "gradient_forward_ratio": (t2 - t1) * 1e3 / fwd_ms,
             "graph_and_autograd_forward_identical": same,
