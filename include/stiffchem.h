@@ -192,6 +192,8 @@ sc_status sc_species_index(const sc_mech *mech, const char *name, int32_t *idx);
  *   "sweep_f", "sweep_b" (uint32, n <= 64 only, 4 per column: mask of the
  *     rows below (above) the diagonal holding an entry, low and high word,
  *     and the first of those entries, then 0),
+ *   "sweep_fi", "sweep_bi" (uint16, n <= 64 only, 64 per column k: the
+ *     entry of row i in column k below (above) the diagonal, else nnz),
  *   "lu_b_lvl", "lu_c_lvl", "fw_lvl", "bw_lvl", "tfw_lvl", "tbw_lvl" (int32
  *     level offsets), "lu_b", "lu_u", "diag" (uint32 items), "lu_c", "fw",
  *     "bw", "tfw", "tbw" (uint64 items), "rxi" (uint16, RXI entries per

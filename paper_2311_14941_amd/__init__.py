@@ -145,7 +145,7 @@ class Mechanism:
                       "tfw_lvl": "int32", "tbw_lvl": "int32", "lu_b": "uint32", "lu_u": "uint32",
                       "diag": "uint32", "lu_c": "uint64", "fw": "uint64", "bw": "uint64", "tfw": "uint64",
                       "tbw": "uint64", "rxi": "uint16", "cstart": "int32", "cmask": "uint64",
-                      "sweep_f": "uint32", "sweep_b": "uint32"}
+                      "sweep_f": "uint32", "sweep_b": "uint32", "sweep_fi": "uint16", "sweep_bi": "uint16"}
 
     def sparse_array(self, name: str):
         """One array of the compiled sparse algebra (sc_mech_sparse_array) as

@@ -237,6 +237,8 @@ sc_status sc_mech_sparse_array(const sc_mech *mech, const char *name, void *out,
     else if (k == "cmask") take(s.cmask);
     else if (k == "sweep_f") take(s.sweep_f);
     else if (k == "sweep_b") take(s.sweep_b);
+    else if (k == "sweep_fi") take(s.sweep_fi);
+    else if (k == "sweep_bi") take(s.sweep_bi);
     else return fail(SC_EINVAL, "unknown sparse array " + k);
     if (out && sz) std::memcpy(out, src, std::min(sz, *bytes));
     *bytes = sz;
@@ -309,7 +311,7 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
         ds.tail0 = S.tail0;
         ds.NV = NV;
         ds.E = 0;
-        ds.C = S.nnz;
+        ds.C = S.nnz + 1;  // E[nnz]: a slot kept at zero (the table sweeps' entry for rows without one)
         ds.G = ds.C + NV;
         ds.H = ds.G + NV;
         ds.WD = ds.H + NV;
@@ -430,7 +432,8 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
              upload(p, S.lu_u, &q.lu_u) && upload(p, S.diag, &q.diag) && upload(p, S.lu_c, &q.lu_c) &&
              upload(p, S.fw, &q.fw) && upload(p, S.bw, &q.bw) && upload(p, rxi, &q.rxi) &&
              upload(p, comp, &q.comp) && upload(p, emap, &q.emap) && upload(p, S.cstart, &q.cstart) &&
-             upload(p, S.cmask, &q.cmask) && upload(p, S.sweep_f, &q.swf) && upload(p, S.sweep_b, &q.swb);
+             upload(p, S.cmask, &q.cmask) && upload(p, S.sweep_f, &q.swf) && upload(p, S.sweep_b, &q.swb) &&
+             upload(p, S.sweep_fi, &q.swfi) && upload(p, S.sweep_bi, &q.swbi);
     }
     if (ok) {
         void *q = nullptr;

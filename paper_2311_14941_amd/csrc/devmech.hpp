@@ -65,6 +65,7 @@ struct DevSparse {
     const int32_t *cstart;   // n + 1: first entry of each column (entries are numbered column by column)
     const uint64_t *cmask;   // 2 n: rows with an entry in column k, lanes 0-63 then 64-127
     const uint32_t *swf, *swb;  // n <= 64: per column the strictly lower (upper) rows' mask and first entry
+    const uint16_t *swfi, *swbi;  // n <= 64: per column and row the lower (upper) entry, or nnz (zero slot)
 };
 constexpr int CMP = 6;  // comp entries per species
 

@@ -62,6 +62,10 @@ struct SparseLU {
     // first of those entries (forward sweep); the same for the rows above
     // the diagonal (backward sweep)
     std::vector<uint32_t> sweep_f, sweep_b;
+    // n <= 64: per column k and row i (64 rows per column), the entry of
+    // (i, k) below (sweep_fi) or above (sweep_bi) the diagonal, else nnz (a
+    // slot the kernels keep at zero)
+    std::vector<uint16_t> sweep_fi, sweep_bi;
     std::vector<uint8_t> apat;    // n * n: structural pattern of the bordered matrix (before fill)
     // LU, level by level: scale the L entries of the level's pivots
     // (b items: e_ik | e_kk << 16), then the Schur updates (c items:

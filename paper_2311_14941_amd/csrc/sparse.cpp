@@ -165,6 +165,8 @@ void compile_sparse(Mech &m)
     S.nnz = (int)S.erow.size();
     S.sweep_f.clear();
     S.sweep_b.clear();
+    S.sweep_fi.clear();
+    S.sweep_bi.clear();
     if (n <= 64) {
         for (int k = 0; k < n; ++k) {
             const uint64_t m = S.cmask[2 * k];
@@ -175,6 +177,15 @@ void compile_sparse(Mech &m)
             for (uint32_t w : {(uint32_t)upper, (uint32_t)(upper >> 32), (uint32_t)S.cstart[k], 0u})
                 S.sweep_b.push_back(w);
         }
+        const int nz = (int)S.erow.size();
+        S.sweep_fi.assign((size_t)n * 64, (uint16_t)nz);
+        S.sweep_bi.assign((size_t)n * 64, (uint16_t)nz);
+        for (int k = 0; k < n; ++k)
+            for (int e = S.cstart[k]; e < S.cstart[k + 1]; ++e) {
+                const int i = S.erow[e];
+                if (i > k) S.sweep_fi[(size_t)k * 64 + i] = (uint16_t)e;
+                if (i < k) S.sweep_bi[(size_t)k * 64 + i] = (uint16_t)e;
+            }
     }
     if (S.nnz >= NOENT) throw Unsupported("sparse LU has too many entries for 16-bit entry indices");
     auto E = [&](int i, int j) { return S.emap[i * n + j]; };

@@ -219,7 +219,7 @@ __device__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const 
     Thermo<> th[VPL];
     const Mix<> x = mixture_v<VPL, G>(m, sp, lds, y, p, th, lane);
 #pragma unroll 4
-    for (int e = lane; e < sp.nnz; e += G) E[e] = 0.0;
+    for (int e = lane; e <= sp.nnz; e += G) E[e] = 0.0;  // and the zero slot E[nnz]
     __syncthreads();
     const double RT = m.Rgas * x.T;
 #pragma unroll 1
@@ -577,10 +577,55 @@ __device__ __forceinline__ double sweep_value(const SweepCol &c, int lane)
         return (c.msk >> lane) & 1 ? c.raw : 0.0;
 }
 
+// With several cells per wave a broadcast is a group shuffle (an LDS-path
+// permute) rather than a readlane, and the three per-column broadcasts of
+// mask and start cost more than a table: there each lane reads its entry
+// in column k from a per-column row table (the zero slot where it has
+// none), four columns ahead, and only the pivot value is broadcast.
+template <int G>
+__device__ __forceinline__ void sweeps_table(const DevSparse &sp, const double *E, const double *DINV, int n,
+                                             int lane, double &z)
+{
+    const int nc = n - 1, zero = sp.nnz;
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        // forward: columns 0 .. n-2 (rows below); backward: n-1 .. 1 (rows above)
+        const uint16_t *ti = (dir == 0 ? sp.swfi : sp.swbi) + lane;
+        auto col = [&](int s) { return dir == 0 ? s : nc - s; };
+        int q[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) q[d] = d < nc ? (int)ti[64 * col(d)] : zero;
+        double v = E[q[0]];
+        int s = 0;
+#pragma unroll 1
+        for (; s + 4 <= nc; s += 4) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int c = s + d;
+                const double vn = c + 1 < nc ? E[q[(d + 1) & 3]] : 0.0;
+                q[d] = c + 4 < nc ? (int)ti[64 * col(c + 4)] : zero;
+                z = fma(-v, gbcast<G>(z, col(c)), z);
+                v = vn;
+            }
+        }
+#pragma unroll 1
+        for (; s < nc; ++s) {
+            const double vn = s + 1 < nc ? E[(int)ti[64 * col(s + 1)]] : 0.0;
+            z = fma(-v, gbcast<G>(z, col(s)), z);
+            v = vn;
+        }
+        if (dir == 0 && lane < n) z *= DINV[lane];
+    }
+}
+
 template <int G>
 __device__ __forceinline__ void sweeps_1(const DevSparse &sp, const double *E, const double *DINV, int n, int lane,
                                          double &z)
 {
+    if constexpr (G < WAVE) {
+        sweeps_table<G>(sp, E, DINV, n, lane, z);
+        return;
+    }
     const bool live = lane < n;
     const uint32_t *f = sp.swf + 4 * (live ? lane : 0), *b = sp.swb + 4 * (live ? lane : 0);
     const int flo = live ? (int)f[0] : 0, fhi = live ? (int)f[1] : 0, fst = live ? (int)f[2] : 0;

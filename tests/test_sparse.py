@@ -137,6 +137,38 @@ def test_schedule_solves_like_numpy(key):
         assert np.allclose(w, np.linalg.solve(A.T, b), rtol=1e-12, atol=1e-12 * np.abs(w).max())
 
 
+@pytest.mark.parametrize("key", ["h2_9", "chon_53"])
+def test_table_sweeps_solve_like_numpy(key):
+    """The solves of the several-cells-per-wave kernels, replayed from their
+    per-column row tables alone ("sweep_fi", "sweep_bi": the entry of each
+    row below / above the diagonal, or nnz, a slot holding zero) on the
+    factors of the schedule replay: equal to numpy.linalg.solve.  A wrong
+    or missing table entry changes the result."""
+    _, cm = mech(key)
+    a = arrays(cm)
+    n = a["perm"].size
+    nnz = a["erow"].size
+    fi = cm.sparse_array("sweep_fi").astype(np.int64).reshape(n, 64)
+    bi = cm.sparse_array("sweep_bi").astype(np.int64).reshape(n, 64)
+    assert np.all(fi[:, n:] == nnz) and np.all(bi[:, n:] == nnz)
+    rng = np.random.default_rng(9)
+    P = a["apat"].reshape(n, n).astype(bool)
+    for trial in range(3):
+        A = np.where(P, rng.normal(size=(n, n)), 0.0)
+        A[np.arange(n), np.arange(n)] = n + rng.uniform(1, 2, n)
+        v = A[a["erow"], a["ecol"]].copy()
+        dinv = Replay(a, rng, cm.info["lu_tail_sparse"]).lu(v)
+        v = np.append(v, 0.0)  # the zero slot
+        b = rng.normal(size=n)
+        z = b.copy()
+        for k in range(n - 1):  # every lane applies column k at once
+            z -= v[fi[k, :n]] * z[k]
+        z *= dinv
+        for k in range(n - 1, 0, -1):
+            z -= v[bi[k, :n]] * z[k]
+        assert np.allclose(z, np.linalg.solve(A, b), rtol=1e-12, atol=1e-12 * np.abs(z).max())
+
+
 @pytest.mark.parametrize("key,width", [("h2_9", 9), ("chon_53", 30), ("chon_110", 64)])
 def test_dense_tail_is_the_widest_full_block(key, width):
     """The register-factorised tail is the widest trailing block of the
