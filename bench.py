@@ -283,6 +283,10 @@ def main():
     res["config"]["plain_launch_ms"] = variants["plain"]["ms"]
     # host-to-host: state from host memory, integrate, results back to host
     res["config"]["host_to_host_ms"] = host_to_host_ms(torch, plan, cells, idx, dev, pred if use_pred else None)
+    if args.linalg == "sparse" and args.method == "ros4":
+        log("bench: interpolated thermodynamics")
+        res["thermo_interp"] = thermo_interp(sc, torch, mech, T, p, Y, dt, out, pred if use_pred else None, launch,
+                                             cpw, reactor, stream, kern_s * 1e3)
     if not constv and not c1 and args.method == "ros4":
         log("bench: parity of the timed output against the stored oracle reference")
         res["parity"] = parity_block(sc, torch, mech, cells, idx, out, T, p, Y, dt, reactor, args)
@@ -346,6 +350,47 @@ def parity_excess(T, Y, Tref, Yref):
     big = np.abs(Yref) > 1e-8
     eY = np.where(big, np.abs(Y - Yref) / (1e-6 * np.abs(Yref) + 1e-300), np.abs(Y - Yref) / 1e-12)
     return np.maximum(eT, eY.max(1))
+
+
+def thermo_interp(sc, torch, mech, T, p, Y, dt, ref, pred, launch, cpw, reactor, stream, exact_ms, tol=1e-9):
+    """The same batch and launch with interpolated thermodynamics (each
+    reaction's -dG/RT and dH/RT from the mechanism compiler's tables in
+    ln T, at most tol absolute error): the tables' degree and size, the
+    kernel time against the exact thermodynamics, and the results against
+    the exact run under the parity bar."""
+    t0 = time.perf_counter()
+    fit = mech.thermo_fit(tol)
+    fit_s = time.perf_counter() - t0
+    plan = sc.Plan(mech, rtol=1e-6, atol=1e-12, reactor=reactor, linalg="sparse", cells_per_wave=cpw,
+                   thermo_tol=tol, **launch)
+    n = T.numel()
+    o = plan.integrate(T, p, Y, dt, out=dict(T=torch.empty_like(T), Y=torch.empty_like(Y),
+                                             status=torch.empty(n, dtype=torch.int32, device=T.device),
+                                             n_acc=torch.zeros(n, dtype=torch.int32, device=T.device),
+                                             n_rej=torch.zeros(n, dtype=torch.int32, device=T.device)))
+    ms = []
+    for _ in range(2):
+        if pred is not None:
+            o["n_acc"].copy_(pred[0])
+            o["n_rej"].copy_(pred[1])
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        o = plan.integrate(T, p, Y, dt, out=o)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    Tt, Yt = o["T"].cpu().numpy(), o["Y"].cpu().numpy().T
+    Te, Ye = ref["T"].cpu().numpy(), ref["Y"].cpu().numpy().T
+    ex = parity_excess(Tt, Yt, Te, Ye)
+    steps = (o["n_acc"] + o["n_rej"]).double().mean().item()
+    return {"tol": tol, "degree": fit["degree"], "intervals": fit["nint"], "range_K": [250.0, 4000.0],
+            "table_bytes": int(fit["coef"].nbytes), "fit_max_err": fit["max_err"], "host_fit_s": fit_s,
+            "kernel_ms": min(ms), "exact_kernel_ms": exact_ms, "speedup": exact_ms / min(ms),
+            "steps_per_cell_mean": steps, "failed_cells": int((o["status"] != 0).sum().item()),
+            "vs_exact_thermo": {"bar": "T and Y > 1e-8 to relative 1e-6, Y <= 1e-8 to absolute 1e-12",
+                                "within_bar": float(np.mean(ex <= 1.0)), "worst_excess": float(ex.max()),
+                                "max_rel_dT": float(np.max(np.abs(Tt - Te) / Te))}}
 
 
 RTOL_SWEEP = (1e-7, 1e-8, 1e-9, 1e-10)

@@ -135,6 +135,20 @@ typedef struct {
                            algebra: SC_EINVAL.  Results agree with one cell per wave to
                            rounding (a cell's reductions and rate sums run over fewer
                            lanes in another order), not bit for bit. */
+    /* Interpolated thermodynamics (paper Sec. 2.5: the chemistry library
+     * interpolates costly thermodynamic functions with polynomials of
+     * optimal degree; sparse linear algebra only).  thermo_tol > 0: each
+     * reaction's -dG/RT and dH/RT are read from piecewise polynomials in
+     * ln T over [thermo_Tmin, thermo_Tmax] (defaults 250 and 4000 K) with
+     * at most thermo_tol absolute error (see sc_mech_thermo_fit) instead
+     * of being summed from the species' NASA-7 values; a cell whose T is
+     * outside the range uses the exact sums.  thermo_degree: the
+     * polynomial degree, 0 (default) = the lowest whose table fits 4 MiB.
+     * 0 (default) = exact.  The VJP and the adjoint refuse such a plan
+     * (their derivatives follow the exact functions). */
+    double thermo_tol;
+    double thermo_Tmin, thermo_Tmax;
+    int32_t thermo_degree;
 } sc_options;
 
 typedef struct {
@@ -206,6 +220,25 @@ sc_status sc_species_index(const sc_mech *mech, const char *name, int32_t *idx);
  * after the levels, with the same operations.
  * SC_EINVAL for an unknown name. */
 sc_status sc_mech_sparse_array(const sc_mech *mech, const char *name, void *out, size_t *bytes);
+
+/* The interpolation tables a plan with thermo_tol > 0 builds (host only).
+ * For each reaction j (mechanism order) the functions
+ *   F1_j(T) = -sum_k nu_kj g_k/(R T),  F2_j(T) = sum_k nu_kj h_k/(R T)
+ * (nu: net coefficients; g, h from the NASA-7 data) are fitted in
+ * u = ln T on nint equal intervals of [ln Tmin, ln Tmax]; on interval i the
+ * polynomial of the degree in t = 2 (u - u_i) / du - 1 interpolates at the
+ * Chebyshev points.  Each degree uses the fewest intervals whose largest
+ * error on a check grid (3 (d+1) + 2 points per interval) is at most tol;
+ * degree = 0 picks the lowest degree (1..8: the cheapest evaluation) whose
+ * table fits 4 MiB (one die's L2 cache), a given degree may use up to 4096
+ * intervals.  Out: *degree_out, *nint_out,
+ * *max_err_out (that check-grid error); coef (may be NULL): nint * R * 2 *
+ * (degree + 1) doubles [interval][reaction][function][power of t], up to
+ * *ncoef of them, *ncoef set to the count.  SC_EINVAL for a bad range, tol or
+ * degree, or when no degree reaches tol. */
+sc_status sc_mech_thermo_fit(const sc_mech *mech, double Tmin, double Tmax, double tol, int32_t degree,
+                             int32_t *degree_out, int32_t *nint_out, double *max_err_out, double *coef,
+                             size_t *ncoef);
 void sc_mech_free(sc_mech *mech);
 
 /* Upload a mechanism's tables to a device (hipSetDevice(device) is made

@@ -40,7 +40,8 @@ class Options(C.Structure):
                 ("mode", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32),
                 ("order", C.c_int32), ("fixed_step", C.c_int32), ("hmax_frac", C.c_double),
                 ("reactor", C.c_int32), ("method", C.c_int32), ("linalg", C.c_int32),
-                ("cells_per_wave", C.c_int32)]
+                ("cells_per_wave", C.c_int32), ("thermo_tol", C.c_double), ("thermo_Tmin", C.c_double),
+                ("thermo_Tmax", C.c_double), ("thermo_degree", C.c_int32)]
 
 
 class Mapping(C.Structure):
@@ -77,6 +78,10 @@ def lib():
         L.sc_mech_info_get.argtypes = [_P, C.POINTER(MechInfo)]
         L.sc_species_index.argtypes = [_P, C.c_char_p, C.POINTER(C.c_int32)]
         L.sc_mech_sparse_array.argtypes = [_P, C.c_char_p, _P, C.POINTER(C.c_size_t)]
+        L.sc_mech_thermo_fit.argtypes = [_P, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                         _P, C.POINTER(C.c_size_t)]
+        L.sc_mech_thermo_fit.restype = C.c_int
         L.sc_mech_sparse_array.restype = C.c_int
         L.sc_mech_free.argtypes = [_P]
         L.sc_mech_free.restype = None
@@ -147,6 +152,22 @@ class Mechanism:
                       "tbw": "uint64", "rxi": "uint16", "cstart": "int32", "cmask": "uint64",
                       "sweep_f": "uint32", "sweep_b": "uint32", "sweep_fi": "uint16", "sweep_bi": "uint16"}
 
+    def thermo_fit(self, tol, Tmin=250.0, Tmax=4000.0, degree=0):
+        """The interpolation tables of the reactions' -dG/RT and dH/RT
+        (sc_mech_thermo_fit, host only): dict with degree, nint, max_err, the
+        grid (u0 = ln Tmin, du) and coef[nint, R, 2, degree + 1]."""
+        import numpy as np
+        d, ni, err, nc = C.c_int32(0), C.c_int32(0), C.c_double(0.0), C.c_size_t(0)
+        _check(lib().sc_mech_thermo_fit(self._h, Tmin, Tmax, tol, degree, C.byref(d), C.byref(ni), C.byref(err),
+                                        None, C.byref(nc)))
+        coef = np.empty(nc.value, dtype=np.float64)
+        _check(lib().sc_mech_thermo_fit(self._h, Tmin, Tmax, tol, degree, C.byref(d), C.byref(ni), C.byref(err),
+                                        coef.ctypes.data_as(C.c_void_p), C.byref(nc)))
+        import math
+        return dict(degree=d.value, nint=ni.value, max_err=err.value, u0=math.log(Tmin),
+                    du=(math.log(Tmax) - math.log(Tmin)) / ni.value,
+                    coef=coef.reshape(ni.value, self.R, 2, d.value + 1))
+
     def sparse_array(self, name: str):
         """One array of the compiled sparse algebra (sc_mech_sparse_array) as
         a NumPy array (host only)."""
@@ -184,7 +205,8 @@ class Plan:
 
     def __init__(self, mech: Mechanism, device: int = 0, rtol=1e-6, atol=1e-12, max_steps=100000,
                  mode="plain", tile=1, grid=0, order="none", fixed_step=False, hmax_frac=0.0,
-                 reactor="const_p", method="ros4", linalg="auto", cells_per_wave=0):
+                 reactor="const_p", method="ros4", linalg="auto", cells_per_wave=0, thermo_tol=0.0,
+                 thermo_Tmin=250.0, thermo_Tmax=4000.0, thermo_degree=0):
         import torch
         self.torch = torch
         self.mech = mech
@@ -199,6 +221,8 @@ class Plan:
         opt.method = METHODS[method]
         opt.linalg = LINALGS[linalg]
         opt.cells_per_wave = int(cells_per_wave)
+        opt.thermo_tol, opt.thermo_Tmin, opt.thermo_Tmax = float(thermo_tol), float(thermo_Tmin), float(thermo_Tmax)
+        opt.thermo_degree = int(thermo_degree)
         self.reactor, self.method, self.linalg = reactor, method, linalg
         self.config = dict(mode=mode, tile=tile, grid=grid, order=order)
         self.options = opt

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INC = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libstiffchem.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["mech.cpp", "sparse.cpp", "capi.cpp", "kernels.hip", "adjoint.hip", "transport.hip", "sparse.hip", "mapping.hip"]
+SOURCES = ["mech.cpp", "sparse.cpp", "thermo_fit.cpp", "capi.cpp", "kernels.hip", "adjoint.hip", "transport.hip", "sparse.hip", "mapping.hip"]
 HEADERS = ["mech.hpp", "devmech.hpp", "core.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -144,6 +144,10 @@ void sc_default_options(sc_options *opt)
     opt->order = 0;
     opt->reactor = SC_REACTOR_CONST_P;
     opt->method = SC_METHOD_ROS4;
+    opt->thermo_tol = 0.0;
+    opt->thermo_Tmin = 250.0;
+    opt->thermo_Tmax = 4000.0;
+    opt->thermo_degree = 0;
 }
 
 sc_status sc_mech_load(const char *text, size_t len, sc_mech **out)
@@ -199,6 +203,27 @@ sc_status sc_mech_info_get(const sc_mech *mech, sc_mech_info *out)
     out->flops_solve_sparse = m.cnt_sparse.flops_solve;
     out->flops_step_sparse = m.cnt_sparse.flops_step;
     out->lu_tail_sparse = m.sp.n - m.sp.tail0;
+    return SC_OK;
+}
+
+sc_status sc_mech_thermo_fit(const sc_mech *mech, double Tmin, double Tmax, double tol, int32_t degree,
+                             int32_t *degree_out, int32_t *nint_out, double *max_err_out, double *coef,
+                             size_t *ncoef)
+{
+    if (!mech) return fail(SC_EINVAL, "mech is NULL");
+    sc::ThermoFit f;
+    try {
+        f = sc::fit_thermo(mech->m, Tmin, Tmax, tol, degree);
+    } catch (const std::exception &e) {
+        return fail(SC_EINVAL, std::string("thermo interpolation: ") + e.what());
+    }
+    if (degree_out) *degree_out = f.degree;
+    if (nint_out) *nint_out = f.nint;
+    if (max_err_out) *max_err_out = f.max_err;
+    if (ncoef) {
+        if (coef) std::copy_n(f.coef.begin(), std::min(*ncoef, f.coef.size()), coef);
+        *ncoef = f.coef.size();
+    }
     return SC_OK;
 }
 
@@ -286,6 +311,17 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
                                          " species; use the sparse one (linalg = SC_LINALG_SPARSE or AUTO)");
     if (sparse && o.method != SC_METHOD_ROS4)
         return fail(SC_EUNSUPPORTED, "the extrapolation baseline runs with the dense linear algebra only");
+    if (!(o.thermo_tol >= 0.0) || !std::isfinite(o.thermo_tol)) return fail(SC_EINVAL, "thermo_tol must be >= 0");
+    if (o.thermo_tol > 0.0 && !sparse)
+        return fail(SC_EUNSUPPORTED, "interpolated thermodynamics run with the sparse linear algebra only");
+    sc::ThermoFit fit;
+    if (o.thermo_tol > 0.0) {
+        try {
+            fit = sc::fit_thermo(mech->m, o.thermo_Tmin, o.thermo_Tmax, o.thermo_tol, o.thermo_degree);
+        } catch (const std::exception &e) {
+            return fail(SC_EINVAL, std::string("thermo interpolation: ") + e.what());
+        }
+    }
     const sc::SparseLU &S = mech->m.sp;
     // the sparse kernels' vectors hold every position of the bordered
     // system (N + 2 of them) in one or two slots per lane
@@ -400,6 +436,20 @@ sc_status sc_plan_create(const sc_mech *mech, int device, const sc_options *opt,
                                t.troe[4 * nt + k], t.troe[5 * nt + k], t.troe[6 * nt + k], 0.0};
     }
     bool ok = upload(p, spv, &d.sp) && upload(p, rx, &d.rx) && upload(p, tr, &d.troe);
+    if (ok && fit.nint > 0) {
+        // the table in the records' execution order: the 64 lanes of a pass
+        // read 64 consecutive coefficient blocks of the cell's interval
+        const int nc = 2 * (fit.degree + 1);
+        std::vector<double> tab(fit.coef.size());
+        for (int iv = 0; iv < fit.nint; ++iv)
+            for (int q = 0; q < t.R; ++q)
+                std::copy_n(&fit.coef[((size_t)iv * t.R + order[q]) * nc], nc, &tab[((size_t)iv * t.R + q) * nc]);
+        ok = upload(p, tab, &ds.itab);
+        ds.ideg = fit.degree;
+        ds.inint = fit.nint;
+        ds.iu0 = fit.u0;
+        ds.iinvdu = 1.0 / fit.du;
+    }
     p->sparse = sparse;
     p->vpl = vpl;
     p->ds = ds;
@@ -689,6 +739,8 @@ sc_status sc_vjp(sc_plan *plan, int64_t n, const double *T, const double *p, con
     sc_status s = check_common(plan, n, ld, {T, p, Y, wT, wY, gT, gY});
     if (s != SC_OK) return s;
     if (plan->dm.cv) return fail(SC_EUNSUPPORTED, "the VJP supports the constant-pressure reactor only");
+    if (plan->ds.itab)
+        return fail(SC_EUNSUPPORTED, "the VJP follows the exact thermodynamics: create the plan with thermo_tol = 0");
     if (plan->m.N + 1 > sc::MAX_STATE)
         return fail(SC_EUNSUPPORTED, "the VJP supports up to " + std::to_string(sc::MAX_STATE - 1) + " species");
     if (n == 0) return SC_OK;
@@ -718,6 +770,8 @@ sc_status sc_adjoint(sc_plan *plan, int64_t n, const double *T0, const double *p
     sc_status s = check_common(plan, n, ld, {T0, p, Y0, dt, gT1, gY1, gT0, gY0, cell_status});
     if (s != SC_OK) return s;
     if (plan->dm.cv) return fail(SC_EUNSUPPORTED, "the adjoint supports the constant-pressure reactor only");
+    if (plan->ds.itab)
+        return fail(SC_EUNSUPPORTED, "the adjoint follows the exact thermodynamics: create the plan with thermo_tol = 0");
     if (plan->opt.method != SC_METHOD_ROS4)
         return fail(SC_EUNSUPPORTED, "the adjoint supports the Rosenbrock method only");
     if (plan->m.N + 1 > sc::MAX_STATE)

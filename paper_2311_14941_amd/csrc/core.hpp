@@ -303,9 +303,22 @@ __device__ __forceinline__ RxRec load_rec(const DevMech &m, int j)
     return r;
 }
 
+// Horner evaluation of the degree-d polynomial with coefficients c[0..d] at t
+__device__ __forceinline__ double poly_t(const double *c, int d, double t)
+{
+    double p = c[d];
+#pragma unroll 1
+    for (int q = d - 1; q >= 0; --q) p = fma(p, t, c[q]);
+    return p;
+}
+
+// itc: with interpolated thermodynamics, this reaction's coefficients of
+// -dG/RT and dH/RT (degree ideg each, in the local coordinate it of the
+// cell's ln T interval) replace the sums over the species' g/RT and h/RT
 template <bool JAC, class S = double>
 __device__ __forceinline__ RxOut<S> reaction(const DevMech &m, const double *lds, const RxRec &rr, const Mix<S> &x,
-                                             double dl, int CO, int GO, int HO, int toff = 0)
+                                             double dl, int CO, int GO, int HO, int toff = 0,
+                                             const double *itc = nullptr, double it = 0.0, int ideg = 0)
 {
     const int kind = rr.kind;
     const int nr = rr.nr, np = rr.np;
@@ -323,11 +336,16 @@ __device__ __forceinline__ RxOut<S> reaction(const DevMech &m, const double *lds
         pn[i] = up ? rr.pnu[i] : 0;
         rc[i] = ur ? lds_get<S>(lds, CO + rs, toff) : S(1.0);
         pc[i] = up ? lds_get<S>(lds, CO + ps, toff) : S(1.0);
+        if (itc) continue;
         dG += pn[i] * (up ? lds_get<S>(lds, GO + ps, toff) : S(0.0)) -
               rn[i] * (ur ? lds_get<S>(lds, GO + rs, toff) : S(0.0));
         if (JAC)
             dH += pn[i] * (up ? lds_get<S>(lds, HO + ps, toff) : S(0.0)) -
                   rn[i] * (ur ? lds_get<S>(lds, HO + rs, toff) : S(0.0));
+    }
+    if (itc) {
+        dG = -poly_t(itc, ideg, it);
+        if (JAC) dH = poly_t(itc + ideg + 1, ideg, it);
     }
     const int dnu = rr.dnu;
     const S lnKc = -dG + dnu * (m.lnp0R - x.lnT);

@@ -66,6 +66,12 @@ struct DevSparse {
     const uint64_t *cmask;   // 2 n: rows with an entry in column k, lanes 0-63 then 64-127
     const uint32_t *swf, *swb;  // n <= 64: per column the strictly lower (upper) rows' mask and first entry
     const uint16_t *swfi, *swbi;  // n <= 64: per column and row the lower (upper) entry, or nnz (zero slot)
+    // interpolated thermodynamics (null: exact): per interval of ln T and
+    // reaction (execution order) the 2 (ideg + 1) coefficients of -dG/RT and
+    // dH/RT in t = 2 (ln T - u_i) iinvdu - 1
+    const double *itab;
+    int ideg, inint;
+    double iu0, iinvdu;
 };
 constexpr int CMP = 6;  // comp entries per species
 

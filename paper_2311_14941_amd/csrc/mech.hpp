@@ -157,6 +157,20 @@ struct Mech {
 // Parse + validate + compile.  Throws ParseError or Unsupported.
 Mech load_mechanism(const std::string &text);
 
+// Interpolation tables of each reaction's -dG/RT and dH/RT in u = ln T
+// (thermo_fit.cpp): per interval, reaction and function the d + 1
+// coefficients of the polynomial in t in [-1, 1].
+constexpr int THERMO_FIT_MAX_DEGREE = 8;
+constexpr int THERMO_FIT_MAX_INTERVALS = 4096;
+constexpr size_t THERMO_FIT_TABLE_BYTES = 4u << 20;  // the optimal degree's table limit
+struct ThermoFit {
+    int degree = 0, nint = 0;
+    double Tmin = 0, Tmax = 0, u0 = 0, du = 0, max_err = 0;
+    std::vector<double> coef;  // [interval][reaction (mechanism order)][2][degree + 1]
+};
+// degree 0: the lowest degree whose table meets tol within THERMO_FIT_TABLE_BYTES
+ThermoFit fit_thermo(const Mech &m, double Tmin, double Tmax, double tol, int degree);
+
 // The sparse compile (sparse.cpp): ordering, symbolic LU, schedules, entry
 // indices and counts of a parsed, validated mechanism.
 void compile_sparse(Mech &m);

@@ -25,6 +25,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "core.hpp"
 
@@ -166,26 +167,64 @@ __device__ __forceinline__ Mix<> mixture_v(const DevMech &m, const DevSparse &sp
     return x;
 }
 
+// A kernel instantiated without the tables sees a null table pointer as a
+// compile-time constant, so the tables' code paths fold away.
+template <bool TB>
+__device__ __forceinline__ DevSparse fix_tables(DevSparse sp)
+{
+    if constexpr (!TB) sp.itab = nullptr;
+    return sp;
+}
+
+// With interpolated thermodynamics: the cell's interval of the table (its
+// reactions' coefficient blocks) and the local coordinate t in [-1, 1];
+// null for exact thermodynamics or a T outside the table's range.
+__device__ __forceinline__ const double *thermo_block(const DevSparse &sp, int R, double lnT, double &t)
+{
+    t = 0.0;
+    if (!sp.itab) return nullptr;
+    const double uu = (lnT - sp.iu0) * sp.iinvdu;
+    if (!(uu >= 0.0) || !(uu < (double)sp.inint)) return nullptr;
+    const int iv = (int)uu;
+    t = 2.0 * (uu - iv) - 1.0;
+    return sp.itab + (size_t)iv * R * 2 * (sp.ideg + 1);
+}
+
 // f(y): dY_k/dt and dT/dt, VPL components per lane (0 beyond N).
 template <int VPL, int G = WAVE>
-__device__ void rhs_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&y)[VPL], double p,
+__device__ __forceinline__ void rhs_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&y)[VPL], double p,
                       const double *dlnA, int lane, double (&f)[VPL])
 {
     const int N = m.N, R = m.R;
     Thermo<> th[VPL];
     const Mix<> x = mixture_v<VPL, G>(m, sp, lds, y, p, th, lane);
+    double itt;
+    const double *itb = thermo_block(sp, R, x.lnT, itt);
     __syncthreads();
+    // the reaction loop, compiled once with the tables and once without (the
+    // exact path's code does not carry the tables' branches)
+    auto pass = [&](auto tables) __attribute__((always_inline)) {
 #pragma unroll 1
-    for (int j = lane; j < R; j += G) {
-        const RxRec rr = load_rec(m, j);
-        const double dl = dlnA ? dlnA[rr.orig] : 0.0;
-        const RxOut<> o = reaction<false>(m, lds, rr, x, dl, sp.C, sp.G, sp.H);
+        for (int j = lane; j < R; j += G) {
+            const RxRec rr = load_rec(m, j);
+            const double dl = dlnA ? dlnA[rr.orig] : 0.0;
+            RxOut<> o;
+            if constexpr (decltype(tables)::value)
+                o = reaction<false>(m, lds, rr, x, dl, sp.C, sp.G, sp.H, 0, itb + (size_t)j * 2 * (sp.ideg + 1), itt,
+                                    sp.ideg);
+            else
+                o = reaction<false>(m, lds, rr, x, dl, sp.C, sp.G, sp.H);
 #pragma unroll
-        for (int i = 0; i < sc::MAXSIDE; ++i) {
-            if (i < rr.nr) atomicAdd(&lds[sp.WD + rr.rsp[i]], -(double)rr.rnu[i] * o.q);
-            if (i < rr.np) atomicAdd(&lds[sp.WD + rr.psp[i]], (double)rr.pnu[i] * o.q);
+            for (int i = 0; i < sc::MAXSIDE; ++i) {
+                if (i < rr.nr) atomicAdd(&lds[sp.WD + rr.rsp[i]], -(double)rr.rnu[i] * o.q);
+                if (i < rr.np) atomicAdd(&lds[sp.WD + rr.psp[i]], (double)rr.pnu[i] * o.q);
+            }
         }
-    }
+    };
+    if (itb)
+        pass(std::true_type{});
+    else
+        pass(std::false_type{});
     __syncthreads();
     double hw[VPL];
 #pragma unroll
@@ -211,7 +250,7 @@ __device__ void rhs_v(const DevMech &m, const DevSparse &sp, double *lds, const 
 // derivatives into the temperature row; the border entries are finished per
 // state component after one barrier.
 template <int VPL, int G = WAVE>
-__device__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&y)[VPL], double p,
+__device__ __forceinline__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const double (&y)[VPL], double p,
                       const double *dlnA, int lane, double inv_hg, double (&f)[VPL])
 {
     const int N = m.N, R = m.R;
@@ -222,11 +261,19 @@ __device__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const 
     for (int e = lane; e <= sp.nnz; e += G) E[e] = 0.0;  // and the zero slot E[nnz]
     __syncthreads();
     const double RT = m.Rgas * x.T;
+    double itt;
+    const double *itb = thermo_block(sp, R, x.lnT, itt);
+    auto pass = [&](auto tables) __attribute__((always_inline)) {
 #pragma unroll 1
     for (int j = lane; j < R; j += G) {
         const RxRec rr = load_rec(m, j);
         const double dl = dlnA ? dlnA[rr.orig] : 0.0;
-        const RxOut<> o = reaction<true>(m, lds, rr, x, dl, sp.C, sp.G, sp.H);
+        RxOut<> o;
+        if constexpr (decltype(tables)::value)
+            o = reaction<true>(m, lds, rr, x, dl, sp.C, sp.G, sp.H, 0, itb + (size_t)j * 2 * (sp.ideg + 1), itt,
+                               sp.ideg);
+        else
+            o = reaction<true>(m, lds, rr, x, dl, sp.C, sp.G, sp.H);
         // the reaction's entry indices are loaded once its rate terms are
         // done, so they do not hold registers through the rate arithmetic
         __builtin_amdgcn_sched_barrier(0);
@@ -263,6 +310,11 @@ __device__ void jac_v(const DevMech &m, const DevSparse &sp, double *lds, const 
         atomicAdd(&E[ix[sc::RXI_TROW + sc::NDEP]], dHJ * o.dT);
         if (m.cv) atomicAdd(&lds[sp.UA + N], dHJ * o.euler);
     }
+    };
+    if (itb)
+        pass(std::true_type{});
+    else
+        pass(std::false_type{});
     __syncthreads();
     const double one = m.cv ? 1.0 : 0.0;
     double hw[VPL], eu[VPL], cpf[VPL], dcp[VPL];
@@ -822,7 +874,7 @@ __device__ __forceinline__ bool bad_input_v(const DevMech &m, const double (&y)[
 }
 
 template <int VPL, int G = WAVE>
-__device__ void integrate_cell_v(const DevMech &m, const DevSparse &sp, const Opts &o, double *lds, int64_t c,
+__device__ __forceinline__ void integrate_cell_v(const DevMech &m, const DevSparse &sp, const Opts &o, double *lds, int64_t c,
                                  int lane, const double *T0, const double *P, const double *Y0, int64_t ld,
                                  const double *DT, const double *dlnA, double *h_io, double *T1, double *Y1,
                                  int32_t *status, int32_t *nacc_out, int32_t *nrej_out, const int32_t *ref)
@@ -866,8 +918,8 @@ __device__ void integrate_cell_v(const DevMech &m, const DevSparse &sp, const Op
     const int grp = (int)threadIdx.x / G;             \
     double *ldsg = lds + (size_t)grp * sp.size;
 
-template <int VPL, bool CV, int CPW>
-__global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp(DevMech mk, DevSparse sp, Opts o, int64_t n,
+template <int VPL, bool CV, int CPW, bool TB>
+__global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp(DevMech mk, DevSparse spk, Opts o, int64_t n,
                                                        const double *T0, const double *P, const double *Y0,
                                                        int64_t ld, const double *DT, const double *dlnA,
                                                        double *h_io, double *T1, double *Y1, int32_t *status,
@@ -875,6 +927,7 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp(DevMech mk, DevSpa
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
+    const DevSparse sp = fix_tables<TB>(spk);
     SP_GEOMETRY
     const int64_t c = (int64_t)blockIdx.x * CPW + grp;
     if (c >= n) return;
@@ -884,8 +937,8 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp(DevMech mk, DevSpa
 
 // Each pull takes tile * CPW queue positions; the wave's groups take them
 // CPW at a time (a group whose position is past the end idles).
-template <int VPL, bool CV, int CPW>
-__global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_persistent(DevMech mk, DevSparse sp, Opts o, int64_t n,
+template <int VPL, bool CV, int CPW, bool TB>
+__global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_persistent(DevMech mk, DevSparse spk, Opts o, int64_t n,
                                                                   const double *T0, const double *P,
                                                                   const double *Y0, int64_t ld, const double *DT,
                                                                   const double *dlnA, double *h_io, double *T1,
@@ -895,6 +948,7 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_persistent(DevMech
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
+    const DevSparse sp = fix_tables<TB>(spk);
     SP_GEOMETRY
 #pragma unroll 1
     while (true) {
@@ -915,8 +969,8 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_persistent(DevMech
     }
 }
 
-template <int VPL, bool CV, int CPW>
-__global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_static(DevMech mk, DevSparse sp, Opts o, int64_t n,
+template <int VPL, bool CV, int CPW, bool TB>
+__global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_static(DevMech mk, DevSparse spk, Opts o, int64_t n,
                                                               const double *T0, const double *P, const double *Y0,
                                                               int64_t ld, const double *DT, const double *dlnA,
                                                               double *h_io, double *T1, double *Y1,
@@ -925,6 +979,7 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_static(DevMech mk,
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
+    const DevSparse sp = fix_tables<TB>(spk);
     SP_GEOMETRY
     const int64_t c0 = (int64_t)blockIdx.x * group;
     const int64_t c1 = min(c0 + group, n);
@@ -934,13 +989,14 @@ __global__ void __launch_bounds__(WAVE) SP_OCC k_integrate_sp_static(DevMech mk,
                                  nrej, ref);
 }
 
-template <int VPL, bool CV, int CPW>
-__global__ void __launch_bounds__(WAVE) k_rhs_sp(DevMech mk, DevSparse sp, int64_t n, const double *T,
+template <int VPL, bool CV, int CPW, bool TB>
+__global__ void __launch_bounds__(WAVE) k_rhs_sp(DevMech mk, DevSparse spk, int64_t n, const double *T,
                                                  const double *P, const double *Y, int64_t ld, const double *dlnA,
                                                  double *fT, double *fY)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
+    const DevSparse sp = fix_tables<TB>(spk);
     SP_GEOMETRY
     const int64_t c = (int64_t)blockIdx.x * CPW + grp;
     if (c >= n) return;
@@ -955,13 +1011,14 @@ __global__ void __launch_bounds__(WAVE) k_rhs_sp(DevMech mk, DevSparse sp, int64
 // sigma border): eliminating sigma, M'_ij = A_ij + A_i,sigma A_sigma,j, and
 // undoing the scaling, J_ij = -(W_i / W_j) M'_ij (species i, j), J_iT =
 // -W_i A_iT, J_Tj = -A_Tj / W_j, J_TT = -A_TT.
-template <int VPL, bool CV, int CPW>
-__global__ void __launch_bounds__(WAVE) k_jac_sp(DevMech mk, DevSparse sp, int64_t n, const double *T,
+template <int VPL, bool CV, int CPW, bool TB>
+__global__ void __launch_bounds__(WAVE) k_jac_sp(DevMech mk, DevSparse spk, int64_t n, const double *T,
                                                  const double *P, const double *Y, int64_t ld, const double *dlnA,
                                                  double *J)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
+    const DevSparse sp = fix_tables<TB>(spk);
     SP_GEOMETRY
     const int64_t c = (int64_t)blockIdx.x * CPW + grp;
     if (c >= n) return;
@@ -988,14 +1045,15 @@ __global__ void __launch_bounds__(WAVE) k_jac_sp(DevMech mk, DevSparse sp, int64
     }
 }
 
-template <int VPL, bool CV, int CPW>
-__global__ void __launch_bounds__(WAVE) k_linsolve_sp(DevMech mk, DevSparse sp, int64_t n, const double *T,
+template <int VPL, bool CV, int CPW, bool TB>
+__global__ void __launch_bounds__(WAVE) k_linsolve_sp(DevMech mk, DevSparse spk, int64_t n, const double *T,
                                                       const double *P, const double *Y, int64_t ld,
                                                       const double *dlnA, const double *hg, const double *b,
                                                       double *x)
 {
     extern __shared__ double lds[];
     const DevMech m = fix_reactor<CV>(mk);
+    const DevSparse sp = fix_tables<TB>(spk);
     SP_GEOMETRY
     const int64_t c = (int64_t)blockIdx.x * CPW + grp;
     if (c >= n) return;
@@ -1020,12 +1078,14 @@ __global__ void __launch_bounds__(WAVE) k_linsolve_sp(DevMech mk, DevSparse sp, 
 // ---------------------------------------------------------------------------
 // launchers (host)
 // ---------------------------------------------------------------------------
-#define SP_KERNEL(k) k<VPLV, CVV, CPWV>
+#define SP_KERNEL(k) k<VPLV, CVV, CPWV, TBV>
 #define SP_CASE(vplv, cpwv, ...)                                                                 \
     if (vpl == (vplv) && cpw == (cpwv)) {                                                        \
         constexpr int VPLV = vplv, CPWV = cpwv;                                                  \
-        if (m.cv) { constexpr bool CVV = true; __VA_ARGS__; }                                   \
-        else { constexpr bool CVV = false; __VA_ARGS__; }                                       \
+        if (m.cv && sp.itab) { constexpr bool CVV = true, TBV = true; __VA_ARGS__; }            \
+        else if (m.cv) { constexpr bool CVV = true, TBV = false; __VA_ARGS__; }                 \
+        else if (sp.itab) { constexpr bool CVV = false, TBV = true; __VA_ARGS__; }              \
+        else { constexpr bool CVV = false, TBV = false; __VA_ARGS__; }                          \
         return hipGetLastError();                                                                \
     }
 #define SP_DISPATCH(...)                   \
@@ -1108,10 +1168,10 @@ int persistent_capacity_sp(int vpl, const DevSparse &sp, int device)
     hipError_t e = hipErrorInvalidValue;
     const int cpw = sp.cpw;
     auto occ = [&](auto kern) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVE, sp_lds(sp, cpw)); };
-    if (vpl == 1 && cpw == 1) e = occ(k_integrate_sp_persistent<1, false, 1>);
-    else if (vpl == 1 && cpw == 2) e = occ(k_integrate_sp_persistent<1, false, 2>);
-    else if (vpl == 1 && cpw == 4) e = occ(k_integrate_sp_persistent<1, false, 4>);
-    else if (vpl == 2 && cpw == 1) e = occ(k_integrate_sp_persistent<2, false, 1>);
+    if (vpl == 1 && cpw == 1) e = occ(k_integrate_sp_persistent<1, false, 1, false>);
+    else if (vpl == 1 && cpw == 2) e = occ(k_integrate_sp_persistent<1, false, 2, false>);
+    else if (vpl == 1 && cpw == 4) e = occ(k_integrate_sp_persistent<1, false, 4, false>);
+    else if (vpl == 2 && cpw == 1) e = occ(k_integrate_sp_persistent<2, false, 1, false>);
     return e == hipSuccess ? per_cu * cus : 0;
 }
 
